@@ -1,0 +1,203 @@
+/*
+ * thoi.h -- C ABI of libthoi.so: Gaussian-copula higher-order-interaction
+ * measures over batches of n-plets on AMD Instinct MI355X (gfx950).
+ *
+ * Method: THOI (arXiv 2501.03381).  For data X with T samples of N variables
+ * the Gaussian-copula covariance Sigma (Supplementary, "Estimation of entropy
+ * via Gaussian copulas", Eq. gaussian_copula_covariance_estimator) gives the
+ * Gaussian entropy of any subset S of variables in closed form
+ * (Supplementary, Eq. gaussian_differential_entropy).  For every selected
+ * n-plet S the library returns the total correlation, dual total correlation,
+ * O-information and S-information (Methods, Eqs. TC, DTC, O-info, S-info),
+ * pairing each n-plet with each of D covariance matrices (Methods, "Parallel
+ * and batched computation of HOI").
+ *
+ * Conventions shared by every call
+ *  - Pointers documented as "device" are HIP device pointers owned by the
+ *    caller; "host" pointers are ordinary host memory read during the call.
+ *    The library keeps no device memory between calls.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Device work is
+ *    enqueued on it and the call returns without synchronising.
+ *  - Argument errors are detected on the host before anything is enqueued and
+ *    returned as a negative thoi_status; nothing is written in that case.
+ *  - Errors found in the data on the device (NaN in X, too many n-plets to
+ *    refine for the workspace) are reported through the int32 status word at
+ *    the start of the workspace (see thoi_ws_status_offset), read by the
+ *    caller after synchronising; it holds THOI_OK or a thoi_status.
+ *  - Numerical failure of one n-plet (a sub-matrix that is not positive
+ *    definite) is not an API error: its outputs are NaN and its flag byte
+ *    has THOI_NPLET_NOT_PD.
+ *  - Units are nats.  Layouts are C order (last index fastest).
+ */
+#ifndef THOI_H_
+#define THOI_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    THOI_OK = 0,
+    THOI_EINVAL = -1,        /* bad argument: shape, pointer, mode or option        */
+    THOI_EUNSUPPORTED = -2,  /* valid request outside the built limits (N, k, T)     */
+    THOI_EWORKSPACE = -3,    /* workspace missing or too small                       */
+    THOI_EHIP = -4,          /* the HIP runtime reported an error on launch          */
+    THOI_EINVAL_DATA = -5    /* device-detected: NaN in the data                     */
+} thoi_status;
+
+/* precision of the per-n-plet evaluation */
+enum { THOI_FP64 = 0, THOI_FP32 = 1, THOI_FP32_REFINE = 2 };
+/* element type of Z or of the output planes */
+enum { THOI_DTYPE_F64 = 0, THOI_DTYPE_F32 = 1 };
+/* n-plet selection */
+enum { THOI_SEL_RANGE = 0, THOI_SEL_LIST = 1, THOI_SEL_MASK = 2 };
+/* per-n-plet flag bits */
+enum { THOI_NPLET_REFINED = 1, THOI_NPLET_NOT_PD = 2 };
+/* which call a workspace is for */
+enum { THOI_WS_COPULIZE = 0, THOI_WS_COV = 1, THOI_WS_EVAL = 2, THOI_WS_BACKWARD = 3 };
+
+/* Built limits. */
+#define THOI_MAX_N_RANGE 62   /* RANGE mode: global indices are int64 and binomials exact in uint64 */
+#define THOI_MAX_N 128        /* variables per covariance matrix (the matrix is staged in LDS)       */
+#define THOI_MAX_K 64         /* largest n-plet order                                              */
+
+/*
+ * Which n-plets to evaluate.  Output position b (0 <= b < B) is:
+ *  RANGE: b-th n-plet of the global enumeration restricted to [g_begin,
+ *         g_begin + g_count).  The global enumeration lists orders kmin..kmax
+ *         in ascending order and, within an order, the k-subsets of
+ *         {0..N-1} in lexicographic order (the order of Python's
+ *         itertools.combinations); g is its 0-based int64 position.  B =
+ *         g_count.  Requires N <= THOI_MAX_N_RANGE.  The count of orders 3..N
+ *         is 2^N - 1 - N - N(N-1)/2 (Supplementary, Eq. comb).
+ *  LIST:  row b of idx (device, [B][kmax_list] int32): strictly ascending
+ *         variable indices in [0, N), then -1 padding.  The order of row b is
+ *         its number of non-negative entries (1 <= k <= THOI_MAX_K).
+ *  MASK:  bit j of mask[b] (device, [B] uint64) selects variable j; N <= 64.
+ */
+typedef struct {
+    int32_t mode;
+    int32_t kmin, kmax;          /* RANGE */
+    int64_t g_begin, g_count;    /* RANGE */
+    const int32_t* idx;          /* LIST, device */
+    int32_t kmax_list;           /* LIST */
+    const uint64_t* mask;        /* MASK, device */
+    int64_t B;                   /* LIST / MASK: number of n-plets */
+} thoi_nplets;
+
+/*
+ * Optional streaming reduction of Omega per (dataset d, order k), replacing
+ * the full output planes (Figure 1A: a per-batch custom function, e.g. the
+ * minimum Omega, aggregated on the fly).  All device arrays are accumulated
+ * across calls (+= / merge), so a long enumeration can be split into RANGE
+ * pieces; the caller initialises them with thoi_reduce_init.
+ *   top_val/top_g: device [D][kmax+1][2][topk]; slot [..][0][..] holds the
+ *     topk largest Omega in descending order, [..][1][..] the topk smallest
+ *     in ascending order; ties are ordered by the lower global index g;
+ *     unused slots have g = -1.
+ *   hist: device [D][kmax+1][hist_bins+2] uint64: bin i counts Omega in
+ *     [lo + i w, lo + (i+1) w) with w = (hi-lo)/hist_bins (Omega == hi goes
+ *     to the last bin), then the counts below lo and above hi.  NaN results
+ *     (not positive definite) are not counted.
+ *   hist_lo_hi: host [kmax+1][2] range per order.
+ */
+typedef struct {
+    int32_t topk;                /* 0 = off; at most 1024 */
+    int32_t hist_bins;           /* 0 = off; at most 4096 */
+    const double* hist_lo_hi;    /* host */
+    double* top_val;             /* device */
+    int64_t* top_g;              /* device */
+    uint64_t* hist;              /* device */
+} thoi_reduce;
+
+typedef struct {
+    int32_t precision;           /* THOI_FP64, THOI_FP32, THOI_FP32_REFINE                      */
+    int32_t out_dtype;           /* THOI_DTYPE_F64 or THOI_DTYPE_F32 for the output planes      */
+    double vif_tau;              /* FP32_REFINE: re-evaluate in FP64 if max_j VIF_j > vif_tau   */
+                                 /* (VIF_j = Sigma_jj (Sigma_S^-1)_jj); <= 0 selects 1e3       */
+    int32_t bias_correct;        /* 1: subtract eta(m) of Eq. bias_corrector from every          */
+                                 /* m-variate entropy, read as 1/2[m log(2/(T-1)) + sum psi]   */
+    int32_t T;                   /* samples per dataset (bias correction only)                  */
+    int32_t write_entropy;       /* 1: a fifth output plane with H(X^n)                          */
+    const thoi_reduce* reduce;   /* host; NULL = write the full output planes                    */
+} thoi_eval_opts;
+
+/*
+ * Gaussian-copula transform (Supplementary, Eq. gaussian_copula_covariance_estimator):
+ * for each dataset and variable, z_t = Phi^{-1}(r_t / (T+1)) with r_t the
+ * 1-based ordinal rank of x_t among the T samples; equal values are ranked by
+ * sample index (-0.0 equals +0.0).
+ *   X: device [D][T][N] FP64.  Z: device [D][T][N], z_dtype F64 or F32.
+ *   ws: device, >= thoi_workspace_bytes(THOI_WS_COPULIZE, D, T, N, NULL, NULL).
+ * A NaN in column (d, n) writes NaN to that column of Z and THOI_EINVAL_DATA to
+ * the workspace status word.  Requires 2 <= T <= 2^31 - 1.
+ */
+thoi_status thoi_copulize(const double* X, int64_t D, int64_t T, int64_t N, int32_t z_dtype,
+                          void* Z, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Covariance operator of the same equation: Sigma_d = (Z_d - mean)^T (Z_d - mean) / (T-1),
+ * accumulated in FP64 on the matrix cores.
+ *   Z: device [D][T][N] (z_dtype).  Sigma: device [D][N][N] FP64 (overwritten).
+ *   ws: device, >= thoi_workspace_bytes(THOI_WS_COV, D, T, N, NULL, NULL).
+ */
+thoi_status thoi_cov(const void* Z, int32_t z_dtype, int64_t D, int64_t T, int64_t N,
+                     double* Sigma, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Measures of every selected n-plet against every covariance matrix.
+ *   Sigma: device [D][N][N] FP64, symmetric.
+ *   out: device [P][D][B] of opts->out_dtype with P = 4 (+1 if write_entropy):
+ *        planes TC, DTC, Omega, S-information (, H(X^n)).  Ignored (may be
+ *        NULL) when opts->reduce is set.
+ *   flags: device [D][B] uint8 (THOI_NPLET_* bits) or NULL.
+ *   ws: device, >= thoi_workspace_bytes(THOI_WS_EVAL, D, 0, N, sel, opts); its
+ *       first 256 bytes are overwritten by the status word and counters.
+ * The per-n-plet work is one Cholesky factorisation of the sub-matrix: the
+ * joint log-determinant and every leave-one-out log-determinant
+ * (log det Sigma_{S\j} = log det Sigma_S + log (Sigma_S^-1)_jj) come from it.
+ */
+thoi_status thoi_nplets_eval(const double* Sigma, int64_t D, int32_t N, const thoi_nplets* sel,
+                             const thoi_eval_opts* opts, void* out, uint8_t* flags,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Adjoint of thoi_nplets_eval: grad_Sigma[d] += sum_b sum_m grad_out[m][d][b] *
+ * d measure_m(b, d) / d Sigma_d, with the entries of Sigma treated as
+ * independent (the result is symmetric).  FP64 factorisation, FP32 accumulation.
+ *   grad_out: device [4][D][B] FP32 (planes TC, DTC, Omega, S).
+ *   grad_Sigma: device [D][N][N] FP32, accumulated.
+ * The bias correction adds constants and has no gradient.  n-plets whose
+ * sub-matrix is not positive definite contribute nothing.  opts->reduce must be NULL.
+ */
+thoi_status thoi_nplets_eval_backward(const double* Sigma, int64_t D, int32_t N, const thoi_nplets* sel,
+                                      const thoi_eval_opts* opts, const float* grad_out,
+                                      float* grad_Sigma, void* ws, size_t ws_bytes, void* stream);
+
+/* Initialise reducer arrays for D datasets (top_g = -1, hist = 0). */
+thoi_status thoi_reduce_init(const thoi_reduce* red, int64_t D, int32_t kmax, void* stream);
+
+/* Device workspace bytes needed by the call `which` (THOI_WS_*); 0 if none. */
+size_t thoi_workspace_bytes(int32_t which, int64_t D, int64_t T, int32_t N,
+                            const thoi_nplets* sel, const thoi_eval_opts* opts);
+/* Offset in bytes of the int32 device status word inside a workspace. */
+size_t thoi_ws_status_offset(void);
+
+/* Host, pure: number of n-plets of orders kmin..kmax of N variables; -1 if it exceeds int64. */
+int64_t thoi_count(int32_t N, int32_t kmin, int32_t kmax);
+/* Host, pure: the n-plet at global index g of the RANGE enumeration (orders kmin..);
+ * writes its order to *out_k and its indices to out_idx[0..k-1]. */
+thoi_status thoi_unrank_host(int32_t N, int32_t kmin, int64_t g, int32_t* out_k, int32_t* out_idx);
+/* Host, pure: bias-correction offsets added to TC and DTC at order k for T samples. */
+thoi_status thoi_bias_offsets(int32_t k, int32_t T, double* d_tc, double* d_dtc, double* eta_k);
+
+const char* thoi_status_string(thoi_status s);
+const char* thoi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* THOI_H_ */

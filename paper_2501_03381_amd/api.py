@@ -1,0 +1,206 @@
+"""Torch-facing calls of the MI355X THOI evaluator.
+
+Torch provides device memory and the current HIP stream; every computation runs in the
+hand-written kernels of ``libthoi.so`` through ``binding``.  All tensors must live on a
+ROCm device (``cuda:N``); nothing here falls back to the CPU.
+
+Typical use::
+
+    Sigma = gc_covariance(X)                    # X: [T, N] or [D, T, N] float64 on cuda
+    out, flags = nplets_measures(Sigma, orders=(3, N), precision="fp32_refine")
+    tc, dtc, omega, s = out                     # each [D, B]
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import binding as B
+
+_PREC = {"fp64": B.THOI_FP64, "fp32": B.THOI_FP32, "fp32_refine": B.THOI_FP32_REFINE}
+_DT = {torch.float64: B.THOI_DTYPE_F64, torch.float32: B.THOI_DTYPE_F32}
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else None
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _require_device(t: torch.Tensor, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor (got {t.device})")
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def device_status(ws: torch.Tensor) -> int:
+    """The int32 status word a call left in its workspace (synchronises)."""
+    off = B.thoi_ws_status_offset()
+    return int(ws[off:off + 4].view(torch.int32).item())
+
+
+def raise_on_device_status(ws: torch.Tensor, fn: str) -> None:
+    st = device_status(ws)
+    if st != B.THOI_OK:
+        raise B.ThoiError(fn, st, B.thoi_status_string(st))
+
+
+# ------------------------------------------------------------------------------------------------ copula / covariance
+def copulize(X: torch.Tensor, z_dtype: torch.dtype = torch.float64, check: bool = True) -> torch.Tensor:
+    """Gaussian-copula transform of X [T, N] or [D, T, N] (float64, sample-major)."""
+    _require_device(X, "X")
+    squeeze = X.dim() == 2
+    Xd = (X[None] if squeeze else X).contiguous()
+    if Xd.dtype != torch.float64:
+        raise TypeError("X must be float64")
+    D, T, N = Xd.shape
+    Z = torch.empty((D, T, N), dtype=z_dtype, device=X.device)
+    nb = B.thoi_workspace_bytes(B.THOI_WS_COPULIZE, D, T, N)
+    ws = _workspace(nb, X.device)
+    B.thoi_copulize(_ptr(Xd), D, T, N, _DT[z_dtype], _ptr(Z), _ptr(ws), ws.numel(), _stream(X.device))
+    if check:
+        raise_on_device_status(ws, "thoi_copulize")
+    return Z[0] if squeeze else Z
+
+
+def cov(Z: torch.Tensor) -> torch.Tensor:
+    """Mean-centred covariance with 1/(T-1) of Z [T, N] or [D, T, N] -> float64 [N, N] or [D, N, N]."""
+    _require_device(Z, "Z")
+    squeeze = Z.dim() == 2
+    Zd = (Z[None] if squeeze else Z).contiguous()
+    D, T, N = Zd.shape
+    S = torch.empty((D, N, N), dtype=torch.float64, device=Z.device)
+    nb = B.thoi_workspace_bytes(B.THOI_WS_COV, D, T, N)
+    ws = _workspace(nb, Z.device)
+    B.thoi_cov(_ptr(Zd), _DT[Zd.dtype], D, T, N, _ptr(S), _ptr(ws), ws.numel(), _stream(Z.device))
+    return S[0] if squeeze else S
+
+
+def gc_covariance(X: torch.Tensor, z_dtype: torch.dtype = torch.float64) -> torch.Tensor:
+    """Sigma_GC(X): copula transform followed by the covariance, both on the GPU."""
+    return cov(copulize(X, z_dtype))
+
+
+# ------------------------------------------------------------------------------------------------ selections
+def range_selection(N: int, kmin: int, kmax: int, g_begin: int = 0, g_count: int | None = None) -> B.ThoiNplets:
+    total = B.thoi_count(N, kmin, kmax)
+    if g_count is None:
+        g_count = total - g_begin
+    return B.ThoiNplets(mode=B.THOI_SEL_RANGE, kmin=kmin, kmax=kmax, g_begin=g_begin, g_count=g_count,
+                        idx=None, kmax_list=0, mask=None, B=0)
+
+
+def list_selection(idx: torch.Tensor) -> B.ThoiNplets:
+    _require_device(idx, "nplets")
+    if idx.dtype != torch.int32 or idx.dim() != 2 or not idx.is_contiguous():
+        raise TypeError("nplets must be a contiguous int32 [B, kmax] tensor padded with -1")
+    return B.ThoiNplets(mode=B.THOI_SEL_LIST, kmin=0, kmax=0, g_begin=0, g_count=0, idx=_ptr(idx),
+                        kmax_list=idx.shape[1], mask=None, B=idx.shape[0])
+
+
+def mask_selection(mask: torch.Tensor) -> B.ThoiNplets:
+    _require_device(mask, "masks")
+    if mask.dtype != torch.int64 or mask.dim() != 1 or not mask.is_contiguous():
+        raise TypeError("masks must be a contiguous int64 [B] tensor (bit j selects variable j)")
+    return B.ThoiNplets(mode=B.THOI_SEL_MASK, kmin=0, kmax=0, g_begin=0, g_count=0, idx=None, kmax_list=0,
+                        mask=_ptr(mask), B=mask.shape[0])
+
+
+def _n_out(sel: B.ThoiNplets) -> int:
+    return sel.g_count if sel.mode == B.THOI_SEL_RANGE else sel.B
+
+
+def make_opts(precision: str = "fp32_refine", out_dtype: torch.dtype = torch.float32, vif_tau: float = 1e3,
+              bias_correct: bool = False, T: int = 0, write_entropy: bool = False) -> B.ThoiEvalOpts:
+    return B.ThoiEvalOpts(precision=_PREC[precision], out_dtype=_DT[out_dtype], vif_tau=float(vif_tau),
+                          bias_correct=int(bool(bias_correct)), T=int(T), write_entropy=int(bool(write_entropy)),
+                          reduce=None)
+
+
+# ------------------------------------------------------------------------------------------------ evaluation
+class Evaluator:
+    """Reusable evaluation of one selection against D covariance matrices of N variables.
+
+    Holds the output, flag and workspace buffers so that repeated calls allocate nothing.
+    """
+
+    def __init__(self, D: int, N: int, sel: B.ThoiNplets, opts: B.ThoiEvalOpts, device, out_dtype=torch.float32,
+                 keep=()):
+        self.D, self.N, self.sel, self.opts = D, N, sel, opts
+        self.keep = keep  # tensors the selection points to
+        self.nout = _n_out(sel)
+        planes = 5 if opts.write_entropy else 4
+        self.out = torch.empty((planes, D, self.nout), dtype=out_dtype, device=device)
+        self.flags = torch.empty((D, self.nout), dtype=torch.uint8, device=device)
+        nb = B.thoi_workspace_bytes(B.THOI_WS_EVAL, D, 0, N, sel, opts)
+        self.ws = _workspace(nb, device)
+        self.device = device
+
+    def __call__(self, Sigma: torch.Tensor, stream=None):
+        S = Sigma if Sigma.dim() == 3 else Sigma[None]
+        if S.dtype != torch.float64 or not S.is_contiguous() or tuple(S.shape) != (self.D, self.N, self.N):
+            raise TypeError(f"Sigma must be contiguous float64 [{self.D}, {self.N}, {self.N}]")
+        st = ctypes.c_void_p(stream) if stream is not None else _stream(self.device)
+        B.thoi_nplets_eval(_ptr(S), self.D, self.N, self.sel, self.opts, _ptr(self.out), _ptr(self.flags),
+                           _ptr(self.ws), self.ws.numel(), st)
+        return self.out, self.flags
+
+    def refine_count(self) -> int:
+        """Number of n-plets the last FP32_REFINE call re-evaluated in FP64 (synchronises)."""
+        return int(self.ws[4:8].view(torch.int32).item())
+
+    def status(self) -> int:
+        return device_status(self.ws)
+
+
+def nplets_measures(Sigma: torch.Tensor, *, orders: tuple[int, int] | None = None,
+                    g_range: tuple[int, int] | None = None, nplets: torch.Tensor | None = None,
+                    masks: torch.Tensor | None = None, precision: str = "fp32_refine",
+                    out_dtype: torch.dtype = torch.float32, vif_tau: float = 1e3, bias_correct: bool = False,
+                    T: int = 0, write_entropy: bool = False, check: bool = True):
+    """(TC, DTC, Omega, S[, H]) of every selected n-plet for every covariance matrix.
+
+    Sigma: float64 [N, N] or [D, N, N] on the device.  Select with exactly one of
+      orders=(kmin, kmax)           all n-plets of those orders (RANGE, optional g_range=(begin, count)),
+      nplets=int32 [B, kmax] tensor ascending indices padded with -1 (LIST),
+      masks=int64 [B] tensor        bit masks over N <= 64 variables (MASK).
+    Returns (out [4 or 5, D, B], flags [D, B] uint8).
+    """
+    _require_device(Sigma, "Sigma")
+    S = (Sigma[None] if Sigma.dim() == 2 else Sigma).contiguous()
+    D, N, _ = S.shape
+    keep = ()
+    if (orders is not None) + (nplets is not None) + (masks is not None) != 1:
+        raise ValueError("give exactly one of orders=, nplets=, masks=")
+    if orders is not None:
+        kmin, kmax = orders
+        if g_range is None:
+            sel = range_selection(N, kmin, kmax)
+        else:
+            sel = range_selection(N, kmin, kmax, g_range[0], g_range[1])
+    elif nplets is not None:
+        nplets = nplets.contiguous()
+        sel, keep = list_selection(nplets), (nplets,)
+    else:
+        masks = masks.contiguous()
+        sel, keep = mask_selection(masks), (masks,)
+    opts = make_opts(precision, out_dtype, vif_tau, bias_correct, T, write_entropy)
+    ev = Evaluator(D, N, sel, opts, S.device, out_dtype, keep)
+    out, flags = ev(S)
+    if check:
+        raise_on_device_status(ev.ws, "thoi_nplets_eval")
+    if Sigma.dim() == 2:
+        return out[:, 0], flags[0]
+    return out, flags
+
+
+# ------------------------------------------------------------------------------------------------ host helpers
+count = B.thoi_count
+unrank = B.thoi_unrank_host
+bias_offsets = B.thoi_bias_offsets

@@ -1,0 +1,271 @@
+// Host side of the libthoi.so C ABI: argument checking, workspace sizing and pure host helpers.
+// Every entry point validates its arguments before enqueuing anything.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <mutex>
+
+#include "thoi_internal.hpp"
+
+namespace thoi {
+
+thoi_status hip_status(hipError_t e) { return e == hipSuccess ? THOI_OK : THOI_EHIP; }
+
+uint64_t binom_u64(int n, int m)
+{
+    if (m < 0 || n < 0 || m > n) return 0;
+    if (m > n - m) m = n - m;
+    // exact for n <= 64: the running value is C(n - m + i, i) and the division is exact
+    unsigned __int128 c = 1;
+    for (int i = 1; i <= m; ++i) c = c * (unsigned __int128)(n - m + i) / (unsigned __int128)i;
+    return (uint64_t)c;
+}
+
+namespace {
+
+// psi at x = (T - j) / 2 for j = 1 .. 65, from the exact finite sums
+//   psi(n)       = -gamma + sum_{i=1}^{n-1} 1/i
+//   psi(n + 1/2) = -gamma - 2 log 2 + sum_{i=1}^{n} 2/(2i - 1)
+// evaluated at the two largest arguments and stepped down with psi(x) = psi(x + 1) - 1/x.
+struct PsiCache {
+    int T = -1;
+    double psi[THOI_MAX_K + 2];  // psi[j] = psi((T - j)/2), j >= 1
+};
+std::mutex g_psi_mu;
+PsiCache g_psi;
+
+double psi_integer_or_half(int twice_x)
+{
+    const double gamma = 0.57721566490153286061;
+    // Kahan-compensated sums, small terms first
+    double s = 0.0, comp = 0.0;
+    auto add = [&](double v) {
+        double y = v - comp;
+        double t = s + y;
+        comp = (t - s) - y;
+        s = t;
+    };
+    if (twice_x % 2 == 0) {
+        const int n = twice_x / 2;
+        for (int i = n - 1; i >= 1; --i) add(1.0 / i);
+        return -gamma + s;
+    }
+    const int n = (twice_x - 1) / 2;
+    for (int i = n; i >= 1; --i) add(2.0 / (2.0 * i - 1.0));
+    return -gamma - 2.0 * log(2.0) + s;
+}
+
+void fill_psi(int T)
+{
+    std::lock_guard<std::mutex> lk(g_psi_mu);
+    if (g_psi.T == T) return;
+    const int jmax = THOI_MAX_K + 1;
+    for (int j = 1; j <= jmax && j < T; ++j) {
+        if (j <= 2) g_psi.psi[j] = psi_integer_or_half(T - j);
+        else g_psi.psi[j] = g_psi.psi[j - 2] - 2.0 / (double)(T - j);   // psi(x) = psi(x+1) - 1/x
+    }
+    g_psi.T = T;
+}
+
+}  // namespace
+
+void bias_offsets(int k, int T, double* d_tc, double* d_dtc, double* eta)
+{
+    *d_tc = *d_dtc = *eta = 0.0;
+    if (k <= 0) return;
+    fill_psi(T);
+    double P = 0.0, Pkm1 = 0.0;
+    for (int j = 1; j <= k; ++j) {
+        if (j == k) Pkm1 = P;
+        P += g_psi.psi[j];
+    }
+    const double psi1 = g_psi.psi[1], psik = g_psi.psi[k];
+    *d_tc = 0.5 * (P - k * psi1);
+    *d_dtc = 0.5 * ((k - 1) * psik - Pkm1);
+    *eta = 0.5 * (k * log(2.0 / (double)(T - 1)) + P);
+}
+
+}  // namespace thoi
+
+using namespace thoi;
+
+namespace {
+
+int64_t count_orders(int N, int kmin, int kmax)
+{
+    if (N < 0 || N > 64) return -1;
+    unsigned __int128 s = 0;
+    for (int k = kmin < 0 ? 0 : kmin; k <= kmax && k <= N; ++k) s += binom_u64(N, k);
+    if (s > (unsigned __int128)INT64_MAX) return -1;
+    return (int64_t)s;
+}
+
+bool valid_dtype(int32_t t) { return t == THOI_DTYPE_F64 || t == THOI_DTYPE_F32; }
+constexpr size_t kLdsLimit = 160 * 1024;
+
+thoi_status check_eval(const double* Sigma, int64_t D, int32_t N, const thoi_nplets* sel, const thoi_eval_opts* opts,
+                       bool forward, const void* out)
+{
+    if (!sel || !opts) return THOI_EINVAL;
+    if (D < 0 || N < 1) return THOI_EINVAL;
+    if (D > 65535 || N > THOI_MAX_N) return THOI_EUNSUPPORTED;
+    if (opts->precision != THOI_FP64 && opts->precision != THOI_FP32 && opts->precision != THOI_FP32_REFINE)
+        return THOI_EINVAL;
+    if (!valid_dtype(opts->out_dtype)) return THOI_EINVAL;
+    int kmax = 0;
+    int64_t B = 0;
+    switch (sel->mode) {
+        case THOI_SEL_RANGE: {
+            if (N > THOI_MAX_N_RANGE) return THOI_EUNSUPPORTED;
+            if (sel->kmin < 0 || sel->kmax < sel->kmin || sel->kmax > N) return THOI_EINVAL;
+            if (sel->kmax > THOI_MAX_K) return THOI_EUNSUPPORTED;
+            const int64_t total = count_orders(N, sel->kmin, sel->kmax);
+            if (total < 0) return THOI_EUNSUPPORTED;
+            if (sel->g_begin < 0 || sel->g_count < 0 || sel->g_begin > total || sel->g_count > total - sel->g_begin)
+                return THOI_EINVAL;
+            kmax = sel->kmax;
+            B = sel->g_count;
+            break;
+        }
+        case THOI_SEL_LIST:
+            if (sel->B < 0 || sel->kmax_list < 1) return THOI_EINVAL;
+            if (sel->kmax_list > THOI_MAX_K) return THOI_EUNSUPPORTED;
+            if (sel->B > 0 && !sel->idx) return THOI_EINVAL;
+            kmax = sel->kmax_list;
+            B = sel->B;
+            break;
+        case THOI_SEL_MASK:
+            if (sel->B < 0) return THOI_EINVAL;
+            if (N > 64) return THOI_EUNSUPPORTED;
+            if (sel->B > 0 && !sel->mask) return THOI_EINVAL;
+            kmax = N;
+            B = sel->B;
+            break;
+        default:
+            return THOI_EINVAL;
+    }
+    if (D * B > 0 && !Sigma) return THOI_EINVAL;
+    if (B > ((int64_t)1 << 40) || D * B > ((int64_t)1 << 42)) return THOI_EUNSUPPORTED;
+    if (opts->bias_correct) {
+        if (opts->bias_correct != 1) return THOI_EINVAL;
+        if (opts->T < kmax + 2 || opts->T < 3) return THOI_EINVAL;
+    }
+    if (opts->write_entropy != 0 && opts->write_entropy != 1) return THOI_EINVAL;
+    if (forward) {
+        if (opts->reduce) return THOI_EUNSUPPORTED;   // streaming reduction: not in this build
+        if (D * B > 0 && !out) return THOI_EINVAL;
+    } else {
+        if (opts->reduce) return THOI_EINVAL;
+    }
+    if (eval_lds_bytes(N, sel, opts) > kLdsLimit) return THOI_EUNSUPPORTED;
+    return THOI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+thoi_status thoi_copulize(const double* X, int64_t D, int64_t T, int64_t N, int32_t z_dtype, void* Z, void* ws,
+                          size_t ws_bytes, void* stream)
+{
+    if (D < 0 || N < 1 || T < 2 || !valid_dtype(z_dtype)) return THOI_EINVAL;
+    if (T > INT32_MAX - 1 || D > 65535 || N > 65535 || D * N > 65535) return THOI_EUNSUPPORTED;
+    if (D > 0 && (!X || !Z)) return THOI_EINVAL;
+    const size_t need = copulize_ws_bytes(D, T, N);
+    if (!ws || ws_bytes < need) return THOI_EWORKSPACE;
+    return launch_copulize(X, D, T, N, z_dtype, Z, ws, (hipStream_t)stream);
+}
+
+thoi_status thoi_cov(const void* Z, int32_t z_dtype, int64_t D, int64_t T, int64_t N, double* Sigma, void* ws,
+                     size_t ws_bytes, void* stream)
+{
+    if (D < 0 || N < 1 || T < 2 || !valid_dtype(z_dtype)) return THOI_EINVAL;
+    if (D > 65535 || N > 4096 || T > ((int64_t)1 << 40)) return THOI_EUNSUPPORTED;
+    if (D > 0 && (!Z || !Sigma)) return THOI_EINVAL;
+    const size_t need = cov_ws_bytes(D, T, N);
+    if (!ws || ws_bytes < need) return THOI_EWORKSPACE;
+    return launch_cov(Z, z_dtype, D, T, N, Sigma, ws, (hipStream_t)stream);
+}
+
+thoi_status thoi_nplets_eval(const double* Sigma, int64_t D, int32_t N, const thoi_nplets* sel,
+                             const thoi_eval_opts* opts, void* out, uint8_t* flags, void* ws, size_t ws_bytes,
+                             void* stream)
+{
+    const thoi_status st = check_eval(Sigma, D, N, sel, opts, true, out);
+    if (st != THOI_OK) return st;
+    return launch_eval(Sigma, D, N, sel, opts, out, flags, ws, ws_bytes, (hipStream_t)stream);
+}
+
+thoi_status thoi_nplets_eval_backward(const double* Sigma, int64_t D, int32_t N, const thoi_nplets* sel,
+                                      const thoi_eval_opts* opts, const float* grad_out, float* grad_Sigma, void* ws,
+                                      size_t ws_bytes, void* stream)
+{
+    const thoi_status st = check_eval(Sigma, D, N, sel, opts, false, nullptr);
+    if (st != THOI_OK) return st;
+    const int64_t B = sel->mode == THOI_SEL_RANGE ? sel->g_count : sel->B;
+    if (D * B > 0 && (!grad_out || !grad_Sigma)) return THOI_EINVAL;
+    return launch_backward(Sigma, D, N, sel, opts, grad_out, grad_Sigma, ws, ws_bytes, (hipStream_t)stream);
+}
+
+thoi_status thoi_reduce_init(const thoi_reduce* red, int64_t D, int32_t kmax, void* stream)
+{
+    (void)red; (void)D; (void)kmax; (void)stream;
+    return THOI_EUNSUPPORTED;
+}
+
+size_t thoi_workspace_bytes(int32_t which, int64_t D, int64_t T, int32_t N, const thoi_nplets* sel,
+                            const thoi_eval_opts* opts)
+{
+    switch (which) {
+        case THOI_WS_COPULIZE: return (D >= 0 && T >= 1 && N >= 1) ? copulize_ws_bytes(D, T, N) : 0;
+        case THOI_WS_COV: return (D >= 0 && T >= 1 && N >= 1) ? cov_ws_bytes(D, T, N) : 0;
+        case THOI_WS_EVAL: return (sel && opts && D >= 0) ? eval_ws_bytes(D, N, sel, opts) : 0;
+        case THOI_WS_BACKWARD: return (sel && opts && D >= 0) ? backward_ws_bytes(D, N, sel, opts) : 0;
+        default: return 0;
+    }
+}
+
+size_t thoi_ws_status_offset(void) { return 0; }
+
+int64_t thoi_count(int32_t N, int32_t kmin, int32_t kmax) { return count_orders(N, kmin, kmax); }
+
+thoi_status thoi_unrank_host(int32_t N, int32_t kmin, int64_t g, int32_t* out_k, int32_t* out_idx)
+{
+    if (N < 1 || N > 64 || kmin < 0 || kmin > N || g < 0 || !out_k || !out_idx) return THOI_EINVAL;
+    int k = kmin;
+    uint64_t r = (uint64_t)g;
+    while (k <= N && r >= binom_u64(N, k)) { r -= binom_u64(N, k); ++k; }
+    if (k > N) return THOI_EINVAL;
+    int x = 0;
+    for (int i = 0; i < k; ++i) {
+        const int m = k - 1 - i;
+        while (r >= binom_u64(N - 1 - x, m)) { r -= binom_u64(N - 1 - x, m); ++x; }
+        out_idx[i] = x++;
+    }
+    *out_k = k;
+    return THOI_OK;
+}
+
+thoi_status thoi_bias_offsets(int32_t k, int32_t T, double* d_tc, double* d_dtc, double* eta_k)
+{
+    if (k < 0 || k > THOI_MAX_K || T < k + 2 || T < 3 || !d_tc || !d_dtc || !eta_k) return THOI_EINVAL;
+    bias_offsets(k, T, d_tc, d_dtc, eta_k);
+    return THOI_OK;
+}
+
+const char* thoi_status_string(thoi_status s)
+{
+    switch (s) {
+        case THOI_OK: return "ok";
+        case THOI_EINVAL: return "invalid argument";
+        case THOI_EUNSUPPORTED: return "unsupported size or option";
+        case THOI_EWORKSPACE: return "workspace missing or too small";
+        case THOI_EHIP: return "HIP runtime error";
+        case THOI_EINVAL_DATA: return "invalid data (NaN in X or bad n-plet row)";
+        default: return "unknown status";
+    }
+}
+
+const char* thoi_version(void) { return "thoi-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

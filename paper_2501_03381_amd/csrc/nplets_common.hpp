@@ -1,0 +1,284 @@
+// Device building blocks of the n-plet evaluation (forward and adjoint), gfx950.
+//
+// Per n-plet S of order k the measures need log det Sigma_S, every leave-one-out
+// log det Sigma_{S\j} and the variances Sigma_jj (Methods, "Parallel and batched computation of
+// HOI").  All four measures are invariant to rescaling each variable, so the kernels work on
+// the correlation matrix R = D^-1/2 Sigma D^-1/2 (unit diagonal) and use one Cholesky
+// factorisation R_S = L L^T per n-plet:
+//   ld   = log det R_S            = sum_j log L_jj^2
+//   a_j  = (R_S^-1)_jj            = sum_{r>=j} (L^-1)_rj^2    (variance-inflation factor VIF_j)
+//   log det R_{S\j} = ld + log a_j                             (cofactor identity)
+// so that, from the Gaussian entropy (Supplementary, Eq. gaussian_differential_entropy) and
+// Eqs. (TC), (DTC), (O-info), (S-info):
+//   TC = -ld/2,  DTC = (ld + sum_j log a_j)/2,  Omega = TC - DTC,  S = TC + DTC.
+#pragma once
+
+#include "thoi_internal.hpp"
+
+namespace thoi {
+
+constexpr double kLn2 = 0.69314718055994530942;
+constexpr double kLog2PiE = 2.8378770664093454836;   // log(2 pi e)
+
+// ------------------------------------------------------------------------------------------------
+// Precision traits
+// ------------------------------------------------------------------------------------------------
+template <typename F> struct Num;
+template <> struct Num<float> {
+    static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+    static __device__ __forceinline__ float mant(float x) { return __builtin_amdgcn_frexp_mantf(x); }
+    static __device__ __forceinline__ int expo(float x) { return __builtin_amdgcn_frexp_expf(x); }
+    static __device__ __forceinline__ float log2m(float m) { return __builtin_amdgcn_logf(m); }   // m in [1/2, 1)
+};
+template <> struct Num<double> {
+    static __device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
+    static __device__ __forceinline__ double mant(double x) { return __builtin_amdgcn_frexp_mant(x); }
+    static __device__ __forceinline__ int expo(double x) { return __builtin_amdgcn_frexp_exp(x); }
+    static __device__ __forceinline__ double log2m(double m) { return log2(m); }
+};
+
+// Running product kept as mantissa * 2^exponent, so products of up to 64 pivots or VIFs never
+// leave the normal range.
+template <typename F> struct LogProd {
+    F m = F(1);
+    int e = 0;
+    __device__ __forceinline__ void mul(F x) { m *= x; }
+    __device__ __forceinline__ void renorm() { e += Num<F>::expo(m); m = Num<F>::mant(m); }
+    __device__ __forceinline__ F log() const { return (Num<F>::log2m(Num<F>::mant(m)) + F(e + Num<F>::expo(m))) * F(kLn2); }
+};
+
+// ------------------------------------------------------------------------------------------------
+// Staging of one dataset into LDS: R (precision F) and log Sigma_jj (FP64).
+// Must be called by the whole block; ends with a barrier.
+// ------------------------------------------------------------------------------------------------
+template <typename F>
+__device__ __forceinline__ void stage_corr(const double* __restrict__ Sig, int N, F* __restrict__ sR,
+                                           double* __restrict__ sIsd, double* __restrict__ sLogd)
+{
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+        const double dj = Sig[(int64_t)j * N + j];
+        sIsd[j] = dj > 0.0 ? 1.0 / sqrt(dj) : __builtin_nan("");
+        sLogd[j] = log(dj);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+        const int i = e / N, j = e - i * N;
+        const double r = (i == j) ? (sIsd[i] == sIsd[i] ? 1.0 : __builtin_nan("")) : Sig[e] * sIsd[i] * sIsd[j];
+        sR[e] = (F)r;
+    }
+    __syncthreads();
+}
+
+// Pascal's triangle C(n, m), n < N, m < kb, into LDS (row stride kb <= 64), computed by wave 0
+// with lane m holding column m.  Caller synchronises afterwards.
+__device__ __forceinline__ void stage_binomials(int N, int kb, uint64_t* __restrict__ sBin)
+{
+    if (threadIdx.x < 64) {
+        const int m = threadIdx.x;
+        uint64_t v = (m == 0) ? 1ull : 0ull;   // row n = 0
+        for (int n = 0; n < N; ++n) {
+            if (n > 0) {
+                const uint32_t lo = __shfl_up((uint32_t)v, 1, 64);
+                const uint32_t hi = __shfl_up((uint32_t)(v >> 32), 1, 64);
+                if (m > 0) v += ((uint64_t)hi << 32) | lo;
+            }
+            if (m < kb) sBin[n * kb + m] = v;
+        }
+    }
+}
+
+// Lexicographic unranking: rank r (0 <= r < C(N, K)) -> the r-th K-subset of {0..N-1} in the
+// order of Python's itertools.combinations.  sBin holds C(n, m) at [n * kb + m], m < kb, kb >= K.
+template <int K>
+__device__ __forceinline__ void unrank_lex(uint64_t r, int N, const uint64_t* __restrict__ sBin, int kb,
+                                           int (&c)[K > 0 ? K : 1])
+{
+    int x = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int m = K - 1 - i;
+        if (m == 0) {
+            c[i] = x + (int)r;
+        } else {
+            while (x < N) {
+                const uint64_t b = sBin[(N - 1 - x) * kb + m];
+                if (r < b) break;
+                r -= b;
+                ++x;
+            }
+            c[i] = x;
+            ++x;
+        }
+    }
+}
+
+// Runtime-order version of the same unranking (one lane).
+__device__ __forceinline__ int unrank_lex_rt(uint64_t r, int N, int k, const uint64_t* __restrict__ sBin, int kb,
+                                             int* __restrict__ c)
+{
+    int x = 0;
+    for (int i = 0; i < k; ++i) {
+        const int m = k - 1 - i;
+        if (m == 0) {
+            c[i] = x + (int)r;
+        } else {
+            while (x < N) {
+                const uint64_t b = sBin[(N - 1 - x) * kb + m];
+                if (r < b) break;
+                r -= b;
+                ++x;
+            }
+            c[i] = x;
+            ++x;
+        }
+    }
+    return k;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Lane engine: one lane factors one n-plet of compile-time order K held in registers.
+// ------------------------------------------------------------------------------------------------
+template <typename F>
+struct FactorOut {
+    F ld;      // log det R_S
+    F sa;      // sum_j log a_j
+    F vmax;    // max_j a_j
+    bool ok;   // every pivot > 0
+};
+
+constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+
+template <typename F, int K>
+__device__ __forceinline__ FactorOut<F> lane_factor(const int (&c)[K > 0 ? K : 1], const F* __restrict__ sR, int N)
+{
+    constexpr int NT = K * (K + 1) / 2;
+    F a[NT > 0 ? NT : 1];
+    // gather the strict lower triangle of R_S; the diagonal is 1
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const F* row = sR + c[i] * N;
+#pragma unroll
+        for (int j = 0; j < i; ++j) a[tri(i, j)] = row[c[j]];
+        a[tri(i, i)] = F(1);
+    }
+    F inv[K > 0 ? K : 1];
+    LogProd<F> det;
+    bool ok = true;
+    // right-looking Cholesky, L overwrites the lower triangle; inv[j] = 1 / L_jj
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const F p = a[tri(j, j)];
+        ok = ok && (p > F(0));
+        const F r = Num<F>::rsq(p);
+        inv[j] = r;
+        det.mul(p);
+        if ((j & 3) == 3) det.renorm();
+#pragma unroll
+        for (int i = j + 1; i < K; ++i) a[tri(i, j)] *= r;
+#pragma unroll
+        for (int i = j + 1; i < K; ++i) {
+            const F lij = a[tri(i, j)];
+#pragma unroll
+            for (int m = j + 1; m <= i; ++m) a[tri(i, m)] -= lij * a[tri(m, j)];
+        }
+    }
+    // W = L^-1 column by column, in place (column j of W replaces column j of L), and the
+    // squared column norms a_j = (R_S^-1)_jj.
+    LogProd<F> va;
+    F vmax = F(0);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const F wjj = inv[j];
+        F acc = wjj * wjj;
+#pragma unroll
+        for (int i = j + 1; i < K; ++i) {
+            F s = a[tri(i, j)] * wjj;
+#pragma unroll
+            for (int m = j + 1; m < i; ++m) s += a[tri(i, m)] * a[tri(m, j)];
+            const F w = -s * inv[i];
+            a[tri(i, j)] = w;
+            acc += w * w;
+        }
+        vmax = vmax > acc ? vmax : acc;
+        va.mul(acc);
+        if ((j & 3) == 3) va.renorm();
+    }
+    FactorOut<F> o;
+    o.ld = det.log();
+    o.sa = va.log();
+    o.vmax = vmax;
+    o.ok = ok;
+    return o;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Wave engine: one wavefront factors one n-plet of runtime order k <= 64 in FP64, the matrix in
+// LDS.  Lane i owns row i.  sM: [64 * ks] doubles with row stride ks >= k + 1; sAux: [2*64].
+// The block must consist of this single wavefront (barriers are block barriers).
+// Returns the FactorOut in every lane.
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) { const double u = __shfl_xor(v, o, 64); v = v > u ? v : u; }
+    return v;
+}
+
+__device__ __forceinline__ FactorOut<double> wave_factor(const double* __restrict__ sR, int N, const int* __restrict__ cidx,
+                                                         int k, double* __restrict__ sM, int ks,
+                                                         double* __restrict__ sInv)
+{
+    const int lane = threadIdx.x & 63;
+    if (lane < k) {
+        const double* row = sR + cidx[lane] * N;
+        for (int j = 0; j < lane; ++j) sM[lane * ks + j] = row[cidx[j]];
+        sM[lane * ks + lane] = 1.0;
+    }
+    __syncthreads();
+    bool ok = true;
+    double lp = 0.0;   // this lane's log pivot (lane j holds log L_jj^2)
+    for (int j = 0; j < k; ++j) {
+        const double p = sM[j * ks + j];
+        ok = ok && (p > 0.0);
+        const double r = rsqrt(p);
+        if (lane == j) { sInv[j] = r; lp = log(p); }
+        if (lane > j && lane < k) sM[lane * ks + j] *= r;
+        __syncthreads();
+        if (lane > j && lane < k) {
+            const double l = sM[lane * ks + j];
+            for (int m = j + 1; m <= lane; ++m) sM[lane * ks + m] -= l * sM[m * ks + j];
+        }
+        __syncthreads();
+    }
+    double la = 0.0, acc = 0.0;
+    if (lane < k) {
+        // column `lane` of W = L^-1 by forward substitution; W_mj is kept in the (unused) upper
+        // triangle of row j = lane.
+        const int j = lane;
+        const double wjj = sInv[j];
+        acc = wjj * wjj;
+        for (int i = j + 1; i < k; ++i) {
+            double s = sM[i * ks + j] * wjj;
+            for (int m = j + 1; m < i; ++m) s += sM[i * ks + m] * sM[j * ks + m];
+            const double w = -s * sInv[i];
+            sM[j * ks + i] = w;
+            acc += w * w;
+        }
+        la = log(acc);
+    }
+    FactorOut<double> o;
+    o.ld = wave_sum(lane < k ? lp : 0.0);
+    o.sa = wave_sum(la);
+    o.vmax = wave_max(acc);
+    o.ok = ok;
+    __syncthreads();
+    return o;
+}
+
+}  // namespace thoi

@@ -1,0 +1,59 @@
+// Internal declarations shared by the libthoi.so translation units (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "thoi.h"
+
+namespace thoi {
+
+// ---------------------------------------------------------------------------------------------
+// Workspace: every call that takes a workspace starts it with this 256-byte header.
+// ---------------------------------------------------------------------------------------------
+struct WsHeader {
+    int32_t status;          // THOI_OK or a thoi_status raised on the device
+    uint32_t refine_count;   // FP32_REFINE: number of n-plets appended to the refine list
+    uint32_t refine_cap;     // capacity of the refine list
+    uint32_t pad0;
+    uint64_t reserved[30];
+};
+static_assert(sizeof(WsHeader) == 256, "workspace header is 256 bytes");
+constexpr size_t kWsHeader = 256;
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Record a device-side error in the status word (first error wins).
+__device__ __forceinline__ void raise_status(WsHeader* h, int32_t code)
+{
+    atomicCAS(&h->status, 0, code);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Host-side helpers (api.cpp).
+// ---------------------------------------------------------------------------------------------
+thoi_status hip_status(hipError_t e);
+// C(n, m) for 0 <= m <= n <= 64, exact in uint64 (0 outside that range).
+uint64_t binom_u64(int n, int m);
+// Bias offsets of order k (see thoi_bias_offsets).
+void bias_offsets(int k, int T, double* d_tc, double* d_dtc, double* eta);
+
+// Launchers implemented in the kernel translation units.
+thoi_status launch_copulize(const double* X, int64_t D, int64_t T, int64_t N, int32_t z_dtype, void* Z,
+                            void* ws, hipStream_t s);
+size_t copulize_ws_bytes(int64_t D, int64_t T, int64_t N);
+thoi_status launch_cov(const void* Z, int32_t z_dtype, int64_t D, int64_t T, int64_t N, double* Sigma,
+                       void* ws, hipStream_t s);
+size_t cov_ws_bytes(int64_t D, int64_t T, int64_t N);
+thoi_status launch_eval(const double* Sigma, int64_t D, int32_t N, const thoi_nplets* sel,
+                        const thoi_eval_opts* opts, void* out, uint8_t* flags, void* ws, size_t ws_bytes,
+                        hipStream_t s);
+size_t eval_ws_bytes(int64_t D, int32_t N, const thoi_nplets* sel, const thoi_eval_opts* opts);
+size_t eval_lds_bytes(int32_t N, const thoi_nplets* sel, const thoi_eval_opts* opts);
+thoi_status launch_backward(const double* Sigma, int64_t D, int32_t N, const thoi_nplets* sel,
+                            const thoi_eval_opts* opts, const float* grad_out, float* grad_Sigma, void* ws,
+                            size_t ws_bytes, hipStream_t s);
+size_t backward_ws_bytes(int64_t D, int32_t N, const thoi_nplets* sel, const thoi_eval_opts* opts);
+thoi_status launch_reduce_init(const thoi_reduce* red, int64_t D, int32_t kmax, hipStream_t s);
+
+}  // namespace thoi

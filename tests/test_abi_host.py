@@ -1,0 +1,136 @@
+"""Host-side checks of the C ABI (no GPU needed): exports, host helpers, argument errors."""
+import ctypes
+import itertools
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "thoi.h")
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2501_03381_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2501_03381_amd import build
+        build.build()
+    binding.lib()
+    return binding
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(thoi_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_library_exports_match(B):
+    declared = _declared()
+    assert set(declared) == set(B.EXPORTS), declared
+    L = B.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_header_constants_match_binding(B):
+    text = open(HEADER).read()
+    for name in ("THOI_MAX_N_RANGE", "THOI_MAX_N", "THOI_MAX_K"):
+        m = re.search(rf"#define {name} (\d+)", text)
+        assert int(m.group(1)) == getattr(B, name)
+
+
+def test_count_matches_eq_comb(B):
+    for n in range(1, 63):
+        assert B.thoi_count(n, 3, n) == (2 ** n - 1 - n - n * (n - 1) // 2 if n >= 3 else 0)
+    assert B.thoi_count(20, 3, 20) == 1048365
+    assert B.thoi_count(30, 3, 30) == 1073741358
+    assert B.thoi_count(64, 0, 64) == -1          # 2^64 does not fit in int64
+    assert B.thoi_count(62, 0, 62) == 2 ** 62
+
+
+def test_unrank_host_brute_force(B):
+    for N in (1, 4, 9, 12):
+        for kmin in (0, 1, 3):
+            if kmin > N:
+                continue
+            ref = [c for k in range(kmin, N + 1) for c in itertools.combinations(range(N), k)]
+            for g, c in enumerate(ref):
+                assert B.thoi_unrank_host(N, kmin, g) == c
+
+
+def test_unrank_host_large_n_samples(B):
+    rng = np.random.default_rng(3)
+    for N in (30, 40, 62):
+        total = B.thoi_count(N, 3, N)
+        for g in rng.integers(0, total, 200):
+            c = B.thoi_unrank_host(N, 3, int(g))
+            k = len(c)
+            # rank back: position of the order block plus the lexicographic rank
+            off = sum(math.comb(N, j) for j in range(3, k))
+            r, x = 0, 0
+            for i, v in enumerate(c):
+                for y in range(x, v):
+                    r += math.comb(N - 1 - y, k - 1 - i)
+                x = v + 1
+            assert off + r == int(g)
+            assert list(c) == sorted(set(c)) and all(0 <= v < N for v in c)
+
+
+def test_bias_offsets_match_oracle(B, orc):
+    """Offsets added to TC / DTC equal what the oracle's literal per-entropy correction adds."""
+    from paper_2501_03381_amd import synth
+    rng = np.random.default_rng(4)
+    A = synth.random_spd(rng, 12, 20.0)
+    for T in (50, 1000, 10001):
+        for k in (1, 2, 3, 7, 12):
+            o0, H0, _ = orc.measures(A, range(k))
+            o1, H1, _ = orc.measures(A, range(k), bias=True, T=T)
+            dtc, ddtc, eta = B.thoi_bias_offsets(k, T)
+            assert abs((o1[0] - o0[0]) - dtc) < 1e-11
+            assert abs((o1[1] - o0[1]) - ddtc) < 1e-11
+            assert abs(eta - orc.bias_eta(k, T)) < 1e-11
+
+
+def test_argument_errors_return_before_launch(B):
+    L = B.lib()
+    sel = B.ThoiNplets(mode=B.THOI_SEL_RANGE, kmin=3, kmax=20, g_begin=0, g_count=10)
+    opts = B.ThoiEvalOpts(precision=B.THOI_FP32_REFINE, out_dtype=B.THOI_DTYPE_F32, vif_tau=1e3)
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation first
+    ev = lambda s, o, N=20, D=1, out=fake: L.thoi_nplets_eval(fake, D, N, ctypes.byref(s), ctypes.byref(o), out, None,
+                                                             fake, 1 << 20, None)
+    bad = B.ThoiNplets(mode=7)
+    assert ev(bad, opts) == B.THOI_EINVAL
+    assert ev(B.ThoiNplets(mode=B.THOI_SEL_RANGE, kmin=3, kmax=21, g_count=1), opts) == B.THOI_EINVAL     # kmax > N
+    assert ev(B.ThoiNplets(mode=B.THOI_SEL_RANGE, kmin=3, kmax=20, g_begin=1048365, g_count=1), opts) == B.THOI_EINVAL
+    assert ev(sel, opts, N=63) == B.THOI_EUNSUPPORTED          # RANGE limited to N <= 62
+    assert ev(sel, opts, D=70000) == B.THOI_EUNSUPPORTED
+    assert ev(sel, opts, out=None) == B.THOI_EINVAL
+    assert ev(sel, B.ThoiEvalOpts(precision=9, out_dtype=1)) == B.THOI_EINVAL
+    assert ev(sel, B.ThoiEvalOpts(precision=0, out_dtype=5)) == B.THOI_EINVAL
+    assert ev(sel, B.ThoiEvalOpts(precision=0, out_dtype=0, bias_correct=1, T=10)) == B.THOI_EINVAL   # T < kmax + 2
+    assert ev(B.ThoiNplets(mode=B.THOI_SEL_LIST, B=5, kmax_list=4, idx=None), opts) == B.THOI_EINVAL
+    assert ev(B.ThoiNplets(mode=B.THOI_SEL_LIST, B=5, kmax_list=65, idx=fake), opts) == B.THOI_EUNSUPPORTED
+    assert ev(B.ThoiNplets(mode=B.THOI_SEL_MASK, B=5, mask=fake), opts, N=65) == B.THOI_EUNSUPPORTED
+    # workspace too small
+    assert L.thoi_nplets_eval(fake, 1, 20, ctypes.byref(sel), ctypes.byref(opts), fake, None, fake, 16, None) == \
+        B.THOI_EWORKSPACE
+    assert L.thoi_copulize(fake, 1, 1, 4, 0, fake, fake, 1 << 20, None) == B.THOI_EINVAL        # T < 2
+    assert L.thoi_copulize(fake, 1, 100, 4, 3, fake, fake, 1 << 20, None) == B.THOI_EINVAL      # dtype
+    assert L.thoi_cov(fake, 0, 1, 100, 4, fake, fake, 0, None) == B.THOI_EWORKSPACE
+    assert B.thoi_status_string(B.THOI_EINVAL_DATA).startswith("invalid data")
+    assert "gfx950" in B.thoi_version()
+
+
+def test_workspace_sizes(B):
+    sel = B.ThoiNplets(mode=B.THOI_SEL_RANGE, kmin=3, kmax=20, g_begin=0, g_count=1048365)
+    o64 = B.ThoiEvalOpts(precision=B.THOI_FP64, out_dtype=B.THOI_DTYPE_F64)
+    o32r = B.ThoiEvalOpts(precision=B.THOI_FP32_REFINE, out_dtype=B.THOI_DTYPE_F32)
+    assert B.thoi_workspace_bytes(B.THOI_WS_EVAL, 1, 0, 20, sel, o64) == 256
+    assert B.thoi_workspace_bytes(B.THOI_WS_EVAL, 1, 0, 20, sel, o32r) >= 256 + 8 * 1048365
+    assert B.thoi_workspace_bytes(B.THOI_WS_COPULIZE, 1, 1000, 10) == 256          # one chunk: no scratch
+    assert B.thoi_workspace_bytes(B.THOI_WS_COPULIZE, 1, 10000, 20) > 10000 * 20 * 12
+    assert B.thoi_ws_status_offset() == 0
