@@ -68,9 +68,10 @@ __global__ __launch_bounds__(64 * kCovWaves) void k_cov_tiles(const void* __rest
         const double b = (in && cb < N) ? ld_z<ZT>(Z, (d * T + t) * N + cb) - mb : 0.0;
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
     }
-    // Output layout of the 16x16x4 FP64 MFMA: lane holds D[4*(lane/16)+v][lane%16], v = 0..3.
+    // Output layout of the 16x16x4 FP64 MFMA: lane holds D[lane/16 + 4v][lane%16], v = 0..3
+    // (checked on gfx950 against the CPU covariance).
 #pragma unroll
-    for (int v = 0; v < 4; ++v) red[w][(4 * (lane >> 4) + v) * 16 + (lane & 15)] = acc[v];
+    for (int v = 0; v < 4; ++v) red[w][((lane >> 4) + 4 * v) * 16 + (lane & 15)] = acc[v];
     __syncthreads();
     for (int e = threadIdx.x; e < 256; e += blockDim.x) {
         double s = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
