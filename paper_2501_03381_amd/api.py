@@ -200,6 +200,80 @@ def nplets_measures(Sigma: torch.Tensor, *, orders: tuple[int, int] | None = Non
     return out, flags
 
 
+# ------------------------------------------------------------------------------------------------ differentiation
+def _selection(N, orders, g_range, nplets, masks):
+    if (orders is not None) + (nplets is not None) + (masks is not None) != 1:
+        raise ValueError("give exactly one of orders=, nplets=, masks=")
+    if orders is not None:
+        kmin, kmax = orders
+        if g_range is None:
+            return range_selection(N, kmin, kmax), ()
+        return range_selection(N, kmin, kmax, g_range[0], g_range[1]), ()
+    if nplets is not None:
+        nplets = nplets.contiguous()
+        return list_selection(nplets), (nplets,)
+    masks = masks.contiguous()
+    return mask_selection(masks), (masks,)
+
+
+def measures_backward(Sigma: torch.Tensor, grad_out: torch.Tensor, *, orders=None, g_range=None, nplets=None,
+                      masks=None, grad_Sigma: torch.Tensor | None = None) -> torch.Tensor:
+    """grad_Sigma [D, N, N] (float32, accumulated) += sum_b sum_m grad_out[m, d, b] d measure_m / d Sigma_d.
+
+    Entries of Sigma are treated as independent; the result is symmetric.
+    """
+    _require_device(Sigma, "Sigma")
+    S = (Sigma[None] if Sigma.dim() == 2 else Sigma).contiguous()
+    D, N, _ = S.shape
+    sel, keep = _selection(N, orders, g_range, nplets, masks)
+    g = grad_out.to(torch.float32)
+    if g.dim() == 2:
+        g = g[:, None]
+    g = g.contiguous()
+    if tuple(g.shape) != (4, D, _n_out(sel)):
+        raise ValueError(f"grad_out must be [4, {D}, {_n_out(sel)}]")
+    if grad_Sigma is None:
+        grad_Sigma = torch.zeros((D, N, N), dtype=torch.float32, device=S.device)
+    opts = make_opts("fp64", torch.float64)
+    ws = _workspace(B.thoi_workspace_bytes(B.THOI_WS_BACKWARD, D, 0, N, sel, opts), S.device)
+    B.thoi_nplets_eval_backward(_ptr(S), D, N, sel, opts, _ptr(g), _ptr(grad_Sigma), _ptr(ws), ws.numel(),
+                                _stream(S.device))
+    del keep
+    return grad_Sigma
+
+
+class NpletsMeasures(torch.autograd.Function):
+    """(TC, DTC, Omega, S) of the selected n-plets as a differentiable function of Sigma.
+
+    forward runs thoi_nplets_eval; backward runs the hand-written adjoint
+    thoi_nplets_eval_backward (FP64 factorisation, FP32 accumulation).
+    """
+
+    @staticmethod
+    def forward(ctx, Sigma, orders=None, g_range=None, nplets=None, masks=None, precision="fp32_refine",
+                out_dtype=torch.float32):
+        out, _ = nplets_measures(Sigma, orders=orders, g_range=g_range, nplets=nplets, masks=masks,
+                                 precision=precision, out_dtype=out_dtype)
+        ctx.save_for_backward(Sigma)
+        ctx.sel = (orders, g_range, nplets, masks)
+        return out[:4]
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (Sigma,) = ctx.saved_tensors
+        orders, g_range, nplets, masks = ctx.sel
+        g = measures_backward(Sigma, grad_out, orders=orders, g_range=g_range, nplets=nplets, masks=masks)
+        g = g.to(Sigma.dtype)
+        if Sigma.dim() == 2:
+            g = g[0]
+        return g, None, None, None, None, None, None
+
+
+def nplets_measures_autograd(Sigma, *, orders=None, g_range=None, nplets=None, masks=None,
+                             precision="fp32_refine", out_dtype=torch.float32):
+    return NpletsMeasures.apply(Sigma, orders, g_range, nplets, masks, precision, out_dtype)
+
+
 # ------------------------------------------------------------------------------------------------ host helpers
 count = B.thoi_count
 unrank = B.thoi_unrank_host

@@ -157,7 +157,8 @@ thoi_status check_eval(const double* Sigma, int64_t D, int32_t N, const thoi_npl
     } else {
         if (opts->reduce) return THOI_EINVAL;
     }
-    if (eval_lds_bytes(N, sel, opts) > kLdsLimit) return THOI_EUNSUPPORTED;
+    if (forward && eval_lds_bytes(N, sel, opts) > kLdsLimit) return THOI_EUNSUPPORTED;
+    if (!forward && backward_lds_bytes(N, sel) > kLdsLimit) return THOI_EUNSUPPORTED;
     return THOI_OK;
 }
 

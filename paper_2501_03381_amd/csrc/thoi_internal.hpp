@@ -54,6 +54,7 @@ thoi_status launch_backward(const double* Sigma, int64_t D, int32_t N, const tho
                             const thoi_eval_opts* opts, const float* grad_out, float* grad_Sigma, void* ws,
                             size_t ws_bytes, hipStream_t s);
 size_t backward_ws_bytes(int64_t D, int32_t N, const thoi_nplets* sel, const thoi_eval_opts* opts);
+size_t backward_lds_bytes(int32_t N, const thoi_nplets* sel);
 thoi_status launch_reduce_init(const thoi_reduce* red, int64_t D, int32_t kmax, hipStream_t s);
 
 }  // namespace thoi
