@@ -102,10 +102,14 @@ typedef struct {
  *     [lo + i w, lo + (i+1) w) with w = (hi-lo)/hist_bins (Omega == hi goes
  *     to the last bin), then the counts below lo and above hi.  NaN results
  *     (not positive definite) are not counted.
- *   hist_lo_hi: host [kmax+1][2] range per order.
+ *   hist_lo_hi: host [kmax+1][2] range per order (lo < hi, finite).
+ * kmax is the selection's largest order: RANGE kmax, LIST kmax_list, MASK N.
+ * In reduce mode no output planes are written (out may be NULL) and the
+ * entropy plane is not produced; n-plets refined in FP64 enter with their
+ * FP64 value.  The workspace must be sized with the same thoi_reduce.
  */
 typedef struct {
-    int32_t topk;                /* 0 = off; at most 1024 */
+    int32_t topk;                /* 0 = off; at most 256 */
     int32_t hist_bins;           /* 0 = off; at most 4096 */
     const double* hist_lo_hi;    /* host */
     double* top_val;             /* device */

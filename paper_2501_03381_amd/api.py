@@ -200,6 +200,71 @@ def nplets_measures(Sigma: torch.Tensor, *, orders: tuple[int, int] | None = Non
     return out, flags
 
 
+# ------------------------------------------------------------------------------------------------ streaming reduction
+class ReduceState:
+    """Per-(dataset, order) top-K / bottom-K Omega lists and Omega histograms, accumulated across
+    calls of ``nplets_reduce`` (so an enumeration can be split into RANGE pieces).
+
+    top_val, top_g: [D, kmax+1, 2, topk] (slot 0: largest Omega descending, slot 1: smallest
+    ascending; g = -1 for unused slots).  hist: [D, kmax+1, bins+2] (bins, then under, over).
+    """
+
+    def __init__(self, D: int, kmax: int, topk: int, hist_bins: int, hist_range, device):
+        import numpy as np
+        self.D, self.kmax, self.topk, self.bins = D, kmax, topk, hist_bins
+        K = max(topk, 1)
+        self.top_val = torch.empty((D, kmax + 1, 2, K), dtype=torch.float64, device=device)
+        self.top_g = torch.empty((D, kmax + 1, 2, K), dtype=torch.int64, device=device)
+        self.hist = torch.empty((D, kmax + 1, max(hist_bins, 0) + 2), dtype=torch.int64, device=device)
+        lohi = np.zeros((kmax + 1, 2), dtype=np.float64)
+        if hist_bins > 0:
+            r = np.asarray(hist_range, dtype=np.float64)
+            lohi[:] = r if r.ndim == 2 else r[None, :]
+        self.lohi = np.ascontiguousarray(lohi)
+        self.struct = B.ThoiReduce(topk=topk, hist_bins=hist_bins,
+                                   hist_lo_hi=self.lohi.ctypes.data_as(ctypes.c_void_p),
+                                   top_val=_ptr(self.top_val), top_g=_ptr(self.top_g), hist=_ptr(self.hist))
+        B.thoi_reduce_init(self.struct, D, kmax, _stream(device))
+
+    def result(self):
+        """Host copies: (top_val, top_g, hist) as NumPy arrays (synchronises)."""
+        return self.top_val.cpu().numpy(), self.top_g.cpu().numpy(), self.hist.cpu().numpy()
+
+
+def nplets_reduce(Sigma: torch.Tensor, *, orders=None, g_range=None, nplets=None, masks=None, topk: int = 100,
+                  hist_bins: int = 256, hist_range=(-10.0, 10.0), precision: str = "fp32_refine",
+                  vif_tau: float = 1e3, bias_correct: bool = False, T: int = 0, state: ReduceState | None = None,
+                  flags: torch.Tensor | None = None, check: bool = True) -> ReduceState:
+    """Streaming reduction of Omega over the selected n-plets (no per-n-plet output).
+
+    hist_range: (lo, hi) for every order, or an array [kmax+1, 2].  Pass `state` from an
+    earlier call to accumulate (e.g. consecutive g_range pieces of one enumeration).
+    """
+    _require_device(Sigma, "Sigma")
+    S = (Sigma[None] if Sigma.dim() == 2 else Sigma).contiguous()
+    D, N, _ = S.shape
+    sel, keep = _selection(N, orders, g_range, nplets, masks)
+    if sel.mode == B.THOI_SEL_RANGE:
+        kmax = sel.kmax
+    elif sel.mode == B.THOI_SEL_LIST:
+        kmax = min(sel.kmax_list, B.THOI_MAX_K)
+    else:
+        kmax = min(N, B.THOI_MAX_K)
+    if state is None:
+        state = ReduceState(D, kmax, topk, hist_bins, hist_range, S.device)
+    if (state.D, state.kmax) != (D, kmax):
+        raise ValueError("state does not match this selection")
+    opts = make_opts(precision, torch.float32, vif_tau, bias_correct, T, False)
+    opts.reduce = ctypes.pointer(state.struct)
+    nb = B.thoi_workspace_bytes(B.THOI_WS_EVAL, D, 0, N, sel, opts)
+    ws = _workspace(nb, S.device)
+    B.thoi_nplets_eval(_ptr(S), D, N, sel, opts, None, _ptr(flags), _ptr(ws), ws.numel(), _stream(S.device))
+    if check:
+        raise_on_device_status(ws, "thoi_nplets_eval")
+    del keep
+    return state
+
+
 # ------------------------------------------------------------------------------------------------ differentiation
 def _selection(N, orders, g_range, nplets, masks):
     if (orders is not None) + (nplets is not None) + (masks is not None) != 1:

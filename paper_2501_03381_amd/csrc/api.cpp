@@ -85,6 +85,13 @@ void bias_offsets(int k, int T, double* d_tc, double* d_dtc, double* eta)
     *eta = 0.5 * (k * log(2.0 / (double)(T - 1)) + P);
 }
 
+void bias_psi_seeds(int T, double* psi1, double* psi2)
+{
+    fill_psi(T);
+    *psi1 = g_psi.psi[1];
+    *psi2 = T > 2 ? g_psi.psi[2] : 0.0;
+}
+
 }  // namespace thoi
 
 using namespace thoi;
@@ -152,8 +159,21 @@ thoi_status check_eval(const double* Sigma, int64_t D, int32_t N, const thoi_npl
     }
     if (opts->write_entropy != 0 && opts->write_entropy != 1) return THOI_EINVAL;
     if (forward) {
-        if (opts->reduce) return THOI_EUNSUPPORTED;   // streaming reduction: not in this build
-        if (D * B > 0 && !out) return THOI_EINVAL;
+        if (opts->reduce) {
+            const thoi_reduce* r = opts->reduce;
+            if (r->topk < 0 || r->hist_bins < 0 || (r->topk == 0 && r->hist_bins == 0)) return THOI_EINVAL;
+            if (r->topk > 256 || r->hist_bins > 4096) return THOI_EUNSUPPORTED;
+            if (r->topk > 0 && (!r->top_val || !r->top_g)) return THOI_EINVAL;
+            if (r->hist_bins > 0) {
+                if (!r->hist || !r->hist_lo_hi) return THOI_EINVAL;
+                for (int k = 0; k <= kmax; ++k) {
+                    const double lo = r->hist_lo_hi[2 * k], hi = r->hist_lo_hi[2 * k + 1];
+                    if (!(lo < hi) || !isfinite(lo) || !isfinite(hi)) return THOI_EINVAL;
+                }
+            }
+        } else if (D * B > 0 && !out) {
+            return THOI_EINVAL;
+        }
     } else {
         if (opts->reduce) return THOI_EINVAL;
     }
@@ -210,8 +230,12 @@ thoi_status thoi_nplets_eval_backward(const double* Sigma, int64_t D, int32_t N,
 
 thoi_status thoi_reduce_init(const thoi_reduce* red, int64_t D, int32_t kmax, void* stream)
 {
-    (void)red; (void)D; (void)kmax; (void)stream;
-    return THOI_EUNSUPPORTED;
+    if (!red || D < 0 || kmax < 0 || kmax > THOI_MAX_K) return THOI_EINVAL;
+    if (red->topk < 0 || red->hist_bins < 0) return THOI_EINVAL;
+    if (red->topk > 256 || red->hist_bins > 4096) return THOI_EUNSUPPORTED;
+    if (D > 0 && red->topk > 0 && (!red->top_val || !red->top_g)) return THOI_EINVAL;
+    if (D > 0 && red->hist_bins > 0 && !red->hist) return THOI_EINVAL;
+    return launch_reduce_init(red, D, kmax, (hipStream_t)stream);
 }
 
 size_t thoi_workspace_bytes(int32_t which, int64_t D, int64_t T, int32_t N, const thoi_nplets* sel,

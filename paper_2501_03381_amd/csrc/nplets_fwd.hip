@@ -2,25 +2,28 @@
 //
 // Work decomposition (replacing the expand-and-index batching of Methods, "Batched
 // sub-covariance matrices", and the identity padding of "padded batches"):
-//  - every workgroup handles one dataset d (grid.y) and one tile of n-plets of ONE order k, so
-//    the order is uniform in the workgroup and the per-order code is fully unrolled;
+//  - every workgroup handles one dataset d (grid.y) and a segment of tiles of n-plets of ONE
+//    order k, so the order is uniform in the workgroup and the per-order code is fully unrolled;
 //  - the dataset's correlation matrix is staged once per workgroup in LDS; an n-plet's
 //    sub-matrix is gathered from there into registers and never exists in HBM;
 //  - RANGE mode unranks each n-plet from its global index in the lane (no index tensors);
 //  - orders are grouped into a few kernel classes by register footprint; each class is one
-//    launch covering all of its orders (per-order tiles are mapped from blockIdx);
+//    launch covering all of its orders (per-order segments are mapped from blockIdx);
 //  - orders above the register classes use one wavefront per n-plet with the matrix in LDS.
 // FP32_REFINE: the FP32 lane engine flags n-plets whose max VIF exceeds tau (or that failed);
 // a follow-up FP64 kernel re-evaluates exactly those and overwrites their results.
+// Results go either to the output planes or to the streaming reducer (reduce_common.hpp).
 #include "nplets_common.hpp"
+#include "reduce_common.hpp"
 
 namespace thoi {
 
 namespace {
 
-constexpr int kTile = 256;          // n-plets (= threads) per lane-engine workgroup
+constexpr int kTile = 256;          // n-plets (= threads) per lane-engine tile
 constexpr int kMaxPieces = 24;      // orders per launch class
-constexpr int kWaveTile = 8;        // n-plets per wave-engine workgroup
+constexpr int kWaveTileOut = 8;     // n-plets per wave-engine workgroup (output mode)
+constexpr int kWaveTileRed = 64;    // n-plets per wave-engine workgroup (reduce mode)
 constexpr int kListOrders = THOI_MAX_K + 2;   // k = 0..64 and one "invalid" bucket
 
 // Kernel classes: [lo, hi] of orders evaluated by one launch of the lane engine.
@@ -33,24 +36,48 @@ constexpr int kF64LaneMax = 18;
 struct Piece {
     int32_t k;
     int32_t pad;
-    int64_t first;   // RANGE: first lexicographic rank inside C(N, k); LIST/MASK: first slot of perm
+    int64_t first;   // RANGE: first lexicographic rank inside C(N, k)
     int64_t pos0;    // RANGE: output position of `first`
     int64_t cnt;     // n-plets in the piece
-    int64_t tile0;   // first tile of the piece inside its launch
+    int64_t blk0;    // first workgroup of the piece inside its launch
 };
 struct PieceTable {
     int32_t n;
     int32_t pad;
     Piece p[kMaxPieces];
 };
-struct BiasTable {   // per order k - lo of the class (or k for the wave engine, up to 64)
-    double dtc[THOI_MAX_K + 1], ddtc[THOI_MAX_K + 1], eta[THOI_MAX_K + 1];
+
+// Bias offsets of Eq. (bias_corrector) are rebuilt on the device from two digamma seeds:
+// psi_j = psi((T-j)/2), psi_j = psi_{j-2} - 2/(T-j).
+struct BiasParams {
+    int32_t on, T;
+    double psi1, psi2;
 };
+
+__device__ __forceinline__ void bias_for(const BiasParams& bp, int k, double& dtc, double& ddtc, double& eta)
+{
+    dtc = ddtc = eta = 0.0;
+    if (!bp.on || k <= 0) return;
+    double pm2 = bp.psi1, pm1 = bp.psi2;   // psi_{j-2}, psi_{j-1} as j advances
+    double P = 0.0, Pkm1 = 0.0, psik = bp.psi1;
+    for (int j = 1; j <= k; ++j) {
+        double pj;
+        if (j == 1) pj = bp.psi1;
+        else if (j == 2) pj = bp.psi2;
+        else { pj = pm2 - 2.0 / (double)(bp.T - j); pm2 = pm1; pm1 = pj; }
+        if (j == k) { Pkm1 = P; psik = pj; }
+        P += pj;
+    }
+    dtc = 0.5 * (P - k * bp.psi1);
+    ddtc = 0.5 * ((k - 1) * psik - Pkm1);
+    eta = 0.5 * (k * log(2.0 / (double)(bp.T - 1)) + P);
+}
 
 struct EvalArgs {
     const double* Sigma;
     int32_t N, D;
     int64_t B;               // output positions per dataset
+    int64_t g_begin;         // RANGE: global index of position 0
     void* out;
     int32_t out_f32, write_H;
     uint8_t* flags;
@@ -59,7 +86,9 @@ struct EvalArgs {
     WsHeader* hdr;
     int64_t* refine_list;
     uint32_t refine_cap;
-    int32_t bias;
+    int32_t seg_tiles;       // lane engine: tiles of kTile n-plets per workgroup
+    int32_t wave_tile;       // wave engine: n-plets per workgroup
+    BiasParams bias;
     // LIST / MASK
     const int32_t* idx;
     int32_t kmax_list;
@@ -67,25 +96,26 @@ struct EvalArgs {
     const int64_t* perm;     // [B] positions sorted by order
     const int64_t* lcnt;     // [kListOrders] per-order counts
     const int64_t* lbase;    // [kListOrders] first slot in perm
-    const int64_t* ltile0;   // [kListOrders] first tile of the order inside its class
+    const int64_t* lblk0;    // [kListOrders] first workgroup of the order inside its launch
 };
 
 // ------------------------------------------------------------------------------------------------
-// Result handling shared by the engines
+// Result handling shared by the engines.  Returns whether the value may enter the reducer.
 // ------------------------------------------------------------------------------------------------
 template <typename F>
-__device__ __forceinline__ void store_result(const EvalArgs& a, int d, int64_t pos, int k, const FactorOut<F>& f,
-                                             double sumlogd, double dtc, double ddtc, double eta,
-                                             bool refine_path)
+__device__ __forceinline__ bool store_result(const EvalArgs& a, bool reduce, int d, int64_t pos, int k,
+                                             const FactorOut<F>& f, double sumlogd, double dtc, double ddtc,
+                                             double eta, bool fp64_pass, double& omega)
 {
     const int64_t o = (int64_t)d * a.B + pos;
     uint8_t flag = 0;
     F TC, DTC;
     const bool finite = isfinite(f.ld) && isfinite(f.sa);
     bool bad = !f.ok || !finite;
-    if (!refine_path && a.precision == THOI_FP32_REFINE) {
+    bool queued = false;
+    if (!fp64_pass && a.precision == THOI_FP32_REFINE) {
         const bool need = bad || !(f.vmax <= (F)a.vif_tau);
-        // wave-aggregated append to the refine list
+        // wave-aggregated append to the refine queue
         const uint64_t ballot = __ballot(need);
         if (ballot) {
             const int lane = threadIdx.x & 63;
@@ -98,9 +128,10 @@ __device__ __forceinline__ void store_result(const EvalArgs& a, int d, int64_t p
                 if (slot < a.refine_cap) a.refine_list[slot] = o;
                 else raise_status(a.hdr, THOI_EWORKSPACE);
                 flag = THOI_NPLET_REFINED;
+                queued = true;
             }
         }
-        bad = false;  // leave the FP32 values; the FP64 pass overwrites them
+        bad = false;  // the FP32 values stay until the FP64 pass overwrites them
     }
     if (bad) {
         TC = DTC = (F)__builtin_nan("");
@@ -110,21 +141,25 @@ __device__ __forceinline__ void store_result(const EvalArgs& a, int d, int64_t p
         DTC = F(0.5) * (f.ld + f.sa) + (F)ddtc;
     }
     const F OM = TC - DTC, SI = TC + DTC;
-    const int64_t plane = (int64_t)a.D * a.B;
-    if (a.out_f32) {
-        float* op = static_cast<float*>(a.out);
-        op[o] = (float)TC; op[plane + o] = (float)DTC; op[2 * plane + o] = (float)OM; op[3 * plane + o] = (float)SI;
-        if (a.write_H) op[4 * plane + o] = bad ? __builtin_nanf("") : (float)(0.5 * (k * kLog2PiE + (double)f.ld + sumlogd) - eta);
-    } else {
-        double* op = static_cast<double*>(a.out);
-        op[o] = (double)TC; op[plane + o] = (double)DTC; op[2 * plane + o] = (double)OM; op[3 * plane + o] = (double)SI;
-        if (a.write_H) op[4 * plane + o] = bad ? __builtin_nan("") : 0.5 * (k * kLog2PiE + (double)f.ld + sumlogd) - eta;
+    omega = (double)OM;
+    if (!reduce) {
+        const int64_t plane = (int64_t)a.D * a.B;
+        if (a.out_f32) {
+            float* op = static_cast<float*>(a.out);
+            op[o] = (float)TC; op[plane + o] = (float)DTC; op[2 * plane + o] = (float)OM; op[3 * plane + o] = (float)SI;
+            if (a.write_H) op[4 * plane + o] = bad ? __builtin_nanf("") : (float)(0.5 * (k * kLog2PiE + (double)f.ld + sumlogd) - eta);
+        } else {
+            double* op = static_cast<double*>(a.out);
+            op[o] = (double)TC; op[plane + o] = (double)DTC; op[2 * plane + o] = (double)OM; op[3 * plane + o] = (double)SI;
+            if (a.write_H) op[4 * plane + o] = bad ? __builtin_nan("") : 0.5 * (k * kLog2PiE + (double)f.ld + sumlogd) - eta;
+        }
     }
     if (a.flags) a.flags[o] = flag;
+    return !bad && !queued;
 }
 
 // ------------------------------------------------------------------------------------------------
-// Lane engine kernels
+// Lane engine
 // ------------------------------------------------------------------------------------------------
 struct LaneCtx {
     int d;
@@ -132,24 +167,29 @@ struct LaneCtx {
     int64_t first, pos0;
     int N;
     int kb;
+    bool reduce;
+    double dtc, ddtc, eta;
 };
 
 template <typename F, int K, int MODE>
-__device__ __forceinline__ void lane_task(const EvalArgs& a, const LaneCtx& cx, const F* sR, const double* sLogd,
-                                          const uint64_t* sBin, const BiasTable& bt, int klo)
+__device__ __forceinline__ bool lane_task(const EvalArgs& a, const LaneCtx& cx, const F* sR, const double* sLogd,
+                                          const uint64_t* sBin, double& omega, int64_t& gidx)
 {
     int c[K > 0 ? K : 1];
     int64_t pos;
     if constexpr (MODE == THOI_SEL_RANGE) {
         unrank_lex<K>((uint64_t)(cx.first + cx.local), cx.N, sBin, cx.kb, c);
         pos = cx.pos0 + cx.local;
+        gidx = a.g_begin + pos;
     } else if constexpr (MODE == THOI_SEL_LIST) {
         pos = a.perm[cx.first + cx.local];
+        gidx = pos;
         const int32_t* row = a.idx + pos * a.kmax_list;
 #pragma unroll
         for (int i = 0; i < K; ++i) c[i] = row[i];
     } else {
         pos = a.perm[cx.first + cx.local];
+        gidx = pos;
         uint64_t m = a.mask[pos];
 #pragma unroll
         for (int i = 0; i < K; ++i) { c[i] = __builtin_ctzll(m); m &= m - 1; }
@@ -160,114 +200,133 @@ __device__ __forceinline__ void lane_task(const EvalArgs& a, const LaneCtx& cx, 
 #pragma unroll
         for (int i = 0; i < K; ++i) sumlogd += sLogd[c[i]];
     }
-    const int e = K - klo;
-    store_result<F>(a, cx.d, pos, K, f, sumlogd, bt.dtc[e], bt.ddtc[e], bt.eta[e], false);
+    return store_result<F>(a, cx.reduce, cx.d, pos, K, f, sumlogd, cx.dtc, cx.ddtc, cx.eta, false, omega);
 }
 
 template <typename F, int K, int KHI, int MODE>
-__device__ __forceinline__ void dispatch_k(int k, const EvalArgs& a, const LaneCtx& cx, const F* sR,
-                                           const double* sLogd, const uint64_t* sBin, const BiasTable& bt, int klo)
+__device__ __forceinline__ bool dispatch_k(int k, const EvalArgs& a, const LaneCtx& cx, const F* sR,
+                                           const double* sLogd, const uint64_t* sBin, double& omega, int64_t& gidx)
 {
-    if (k == K) {
-        lane_task<F, K, MODE>(a, cx, sR, sLogd, sBin, bt, klo);
-        return;
-    }
-    if constexpr (K < KHI) dispatch_k<F, K + 1, KHI, MODE>(k, a, cx, sR, sLogd, sBin, bt, klo);
+    if (k == K) return lane_task<F, K, MODE>(a, cx, sR, sLogd, sBin, omega, gidx);
+    if constexpr (K < KHI) return dispatch_k<F, K + 1, KHI, MODE>(k, a, cx, sR, sLogd, sBin, omega, gidx);
+    return false;
 }
 
-// LDS: sR [N*N] F | sIsd [N] f64 | sLogd [N] f64 | sBin [N*kb] u64
-__host__ __device__ inline size_t lane_lds_bytes(int N, int kb, int fsize)
+// LDS: sR [N*N] F | sIsd [N] f64 | sLogd [N] f64 | sBin [N*kb] u64 | (reduce) RedLds
+__host__ __device__ inline size_t lane_stage_bytes(int N, int kb, int fsize)
 {
     size_t off = (size_t)N * N * fsize;
-    off = (off + 7) / 8 * 8;
+    off = (off + 15) / 16 * 16;
     off += (size_t)N * 8 * 2;
     off += (size_t)N * kb * 8;
-    return off;
+    return (off + 15) / 16 * 16;
 }
 
-template <typename F, int KLO, int KHI, int MODE>
-__global__ __launch_bounds__(kTile) void k_eval_lane(EvalArgs a, PieceTable tab, BiasTable bt)
+template <typename F, int KLO, int KHI, int MODE, bool RED>
+__global__ __launch_bounds__(kTile) void k_eval_lane(EvalArgs a, PieceTable tab, RedArgs red)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double sbias[3];
     const int N = a.N;
     const int d = blockIdx.y;
-    const int64_t tile = blockIdx.x;
-    // which order / piece does this tile belong to (uniform in the workgroup)
+    const int64_t blk = blockIdx.x;
+    const int64_t per_blk = (int64_t)kTile * a.seg_tiles;
+    // which order / piece does this workgroup belong to (uniform in the workgroup)
     int k = -1;
-    int64_t first = 0, pos0 = 0, cnt = 0, tile0 = 0;
+    int64_t first = 0, pos0 = 0, cnt = 0, blk0 = 0;
     if constexpr (MODE == THOI_SEL_RANGE) {
         for (int p = 0; p < tab.n; ++p) {
-            const int64_t nt = (tab.p[p].cnt + kTile - 1) / kTile;
-            if (tile >= tab.p[p].tile0 && tile < tab.p[p].tile0 + nt) {
-                k = tab.p[p].k; first = tab.p[p].first; pos0 = tab.p[p].pos0; cnt = tab.p[p].cnt; tile0 = tab.p[p].tile0;
+            const int64_t nb = (tab.p[p].cnt + per_blk - 1) / per_blk;
+            if (blk >= tab.p[p].blk0 && blk < tab.p[p].blk0 + nb) {
+                k = tab.p[p].k; first = tab.p[p].first; pos0 = tab.p[p].pos0; cnt = tab.p[p].cnt; blk0 = tab.p[p].blk0;
             }
         }
     } else {
         for (int kk = KLO; kk <= KHI; ++kk) {
             const int64_t c = a.lcnt[kk];
-            const int64_t nt = (c + kTile - 1) / kTile;
-            const int64_t t0 = a.ltile0[kk];
-            if (c > 0 && tile >= t0 && tile < t0 + nt) { k = kk; first = a.lbase[kk]; cnt = c; tile0 = t0; }
+            const int64_t nb = (c + per_blk - 1) / per_blk;
+            const int64_t b0 = a.lblk0[kk];
+            if (c > 0 && blk >= b0 && blk < b0 + nb) { k = kk; first = a.lbase[kk]; cnt = c; blk0 = b0; }
         }
     }
     if (k < 0) return;
 
     const int kb = (MODE == THOI_SEL_RANGE) ? KHI : 0;
     F* sR = reinterpret_cast<F*>(smem);
-    size_t off = ((size_t)N * N * sizeof(F) + 7) / 8 * 8;
+    const size_t off = ((size_t)N * N * sizeof(F) + 15) / 16 * 16;
     double* sIsd = reinterpret_cast<double*>(smem + off);
     double* sLogd = sIsd + N;
     uint64_t* sBin = reinterpret_cast<uint64_t*>(sLogd + N);
+    RedLds& S = *reinterpret_cast<RedLds*>(smem + lane_stage_bytes(N, kb, sizeof(F)));
+    if (threadIdx.x == 0) bias_for(a.bias, k, sbias[0], sbias[1], sbias[2]);
     if constexpr (MODE == THOI_SEL_RANGE) stage_binomials(N, kb, sBin);
     stage_corr<F>(a.Sigma + (int64_t)d * N * N, N, sR, sIsd, sLogd);
+    constexpr bool reduce = RED;
+    if constexpr (RED) red_begin(S, red.topk, red.bins);
 
     LaneCtx cx;
     cx.d = d;
-    cx.local = (tile - tile0) * kTile + threadIdx.x;
     cx.first = first;
     cx.pos0 = pos0;
     cx.N = N;
     cx.kb = kb;
-    const bool active = cx.local < cnt;
-    if (active) dispatch_k<F, KLO, KHI, MODE>(k, a, cx, sR, sLogd, sBin, bt, KLO);
+    cx.reduce = reduce;
+    cx.dtc = sbias[0];
+    cx.ddtc = sbias[1];
+    cx.eta = sbias[2];
+    const int64_t base = (blk - blk0) * per_blk;
+    for (int t = 0; t < a.seg_tiles; ++t) {
+        const int64_t tb = base + (int64_t)t * kTile;
+        if (tb >= cnt) break;                         // uniform: same for the whole workgroup
+        cx.local = tb + threadIdx.x;
+        double omega = 0.0;
+        int64_t gidx = 0;
+        bool valid = false;
+        if (cx.local < cnt) valid = dispatch_k<F, KLO, KHI, MODE>(k, a, cx, sR, sLogd, sBin, omega, gidx);
+        if constexpr (RED) red_push(S, red, k, valid, omega, gidx);
+    }
+    if constexpr (RED) red_end(S, red, a.hdr, d, k);
 }
 
 // ------------------------------------------------------------------------------------------------
 // Wave engine kernel: orders above the register classes (one wavefront per n-plet, FP64).
-// grid (tiles, D), block 64.  For RANGE a PieceTable of the orders; for LIST/MASK the device
-// per-order table restricted to [klo, 64].
-// LDS: sR [N*N] f64 | sIsd [N] | sLogd [N] | sBin [N*64] | sM [64*ks] | sInv [64] | cidx [64] int
+// grid (workgroups, D), block 64.
+// LDS: sR [N*N] f64 | sIsd [N] | sLogd [N] | sBin [N*64] (RANGE) | sM [64*ks] | sInv [64] |
+//      cidx [64] int | res_v [64] | res_g [64] | res_ok [64] | (reduce) RedLds
 // ------------------------------------------------------------------------------------------------
-__host__ __device__ inline size_t wave_lds_bytes(int N, int kmax, bool with_bin)
+__host__ __device__ inline size_t wave_stage_bytes(int N, int kmax, bool with_bin)
 {
     const int ks = kmax + 1;
     size_t off = (size_t)N * N * 8 + (size_t)N * 16 + (with_bin ? (size_t)N * 64 * 8 : 0);
     off += (size_t)64 * ks * 8 + 64 * 8 + 64 * 4;
-    return off;
+    off += 64 * 8 + 64 * 8 + 64 * 4;
+    return (off + 15) / 16 * 16;
 }
 
-template <int MODE>
-__global__ __launch_bounds__(64) void k_eval_wave(EvalArgs a, PieceTable tab, BiasTable bt, int klo, int kmax)
+template <int MODE, bool RED>
+__global__ __launch_bounds__(64) void k_eval_wave(EvalArgs a, PieceTable tab, RedArgs red, int klo, int kmax)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double sbias[3];
     const int N = a.N;
     const int d = blockIdx.y;
-    const int64_t tile = blockIdx.x;
+    const int64_t blk = blockIdx.x;
+    const int wt = a.wave_tile;
     int k = -1;
-    int64_t first = 0, pos0 = 0, cnt = 0, tile0 = 0;
+    int64_t first = 0, pos0 = 0, cnt = 0, blk0 = 0;
     if constexpr (MODE == THOI_SEL_RANGE) {
         for (int p = 0; p < tab.n; ++p) {
-            const int64_t nt = (tab.p[p].cnt + kWaveTile - 1) / kWaveTile;
-            if (tile >= tab.p[p].tile0 && tile < tab.p[p].tile0 + nt) {
-                k = tab.p[p].k; first = tab.p[p].first; pos0 = tab.p[p].pos0; cnt = tab.p[p].cnt; tile0 = tab.p[p].tile0;
+            const int64_t nb = (tab.p[p].cnt + wt - 1) / wt;
+            if (blk >= tab.p[p].blk0 && blk < tab.p[p].blk0 + nb) {
+                k = tab.p[p].k; first = tab.p[p].first; pos0 = tab.p[p].pos0; cnt = tab.p[p].cnt; blk0 = tab.p[p].blk0;
             }
         }
     } else {
         for (int kk = klo; kk <= kmax; ++kk) {
             const int64_t c = a.lcnt[kk];
-            const int64_t nt = (c + kWaveTile - 1) / kWaveTile;
-            const int64_t t0 = a.ltile0[kk];
-            if (c > 0 && tile >= t0 && tile < t0 + nt) { k = kk; first = a.lbase[kk]; cnt = c; tile0 = t0; }
+            const int64_t nb = (c + wt - 1) / wt;
+            const int64_t b0 = a.lblk0[kk];
+            if (c > 0 && blk >= b0 && blk < b0 + nb) { k = kk; first = a.lbase[kk]; cnt = c; blk0 = b0; }
         }
     }
     if (k < 0) return;
@@ -279,39 +338,63 @@ __global__ __launch_bounds__(64) void k_eval_wave(EvalArgs a, PieceTable tab, Bi
     double* sM = reinterpret_cast<double*>(sBin + (MODE == THOI_SEL_RANGE ? N * 64 : 0));
     double* sInv = sM + 64 * ks;
     int* cidx = reinterpret_cast<int*>(sInv + 64);
+    double* res_v = reinterpret_cast<double*>(cidx + 64);
+    int64_t* res_g = reinterpret_cast<int64_t*>(res_v + 64);
+    int* res_ok = reinterpret_cast<int*>(res_g + 64);
+    RedLds& S = *reinterpret_cast<RedLds*>(smem + wave_stage_bytes(N, kmax, MODE == THOI_SEL_RANGE));
+    if (threadIdx.x == 0) bias_for(a.bias, k, sbias[0], sbias[1], sbias[2]);
     if constexpr (MODE == THOI_SEL_RANGE) stage_binomials(N, 64, sBin);
     stage_corr<double>(a.Sigma + (int64_t)d * N * N, N, sR, sIsd, sLogd);
+    constexpr bool reduce = RED;
+    if constexpr (RED) red_begin(S, red.topk, red.bins);
 
     const int lane = threadIdx.x;
-    const int64_t l0 = (tile - tile0) * kWaveTile;
-    const int64_t l1 = l0 + kWaveTile < cnt ? l0 + kWaveTile : cnt;
-    for (int64_t l = l0; l < l1; ++l) {
-        int64_t pos;
-        if constexpr (MODE == THOI_SEL_RANGE) {
-            if (lane == 0) unrank_lex_rt((uint64_t)(first + l), N, k, sBin, 64, cidx);
-            pos = pos0 + l;
-        } else if constexpr (MODE == THOI_SEL_LIST) {
-            pos = a.perm[first + l];
-            if (lane < k) cidx[lane] = a.idx[pos * a.kmax_list + lane];
-        } else {
-            pos = a.perm[first + l];
-            if (lane == 0) {
-                uint64_t m = a.mask[pos];
-                for (int i = 0; i < k; ++i) { cidx[i] = __builtin_ctzll(m); m &= m - 1; }
+    const int64_t l0 = (blk - blk0) * wt;
+    const int64_t l1 = l0 + wt < cnt ? l0 + wt : cnt;
+    for (int64_t c0 = l0; c0 < l1; c0 += 64) {
+        const int64_t c1 = c0 + 64 < l1 ? c0 + 64 : l1;
+        for (int64_t l = c0; l < c1; ++l) {
+            int64_t pos, gidx;
+            if constexpr (MODE == THOI_SEL_RANGE) {
+                if (lane == 0) unrank_lex_rt((uint64_t)(first + l), N, k, sBin, 64, cidx);
+                pos = pos0 + l;
+                gidx = a.g_begin + pos;
+            } else if constexpr (MODE == THOI_SEL_LIST) {
+                pos = a.perm[first + l];
+                gidx = pos;
+                if (lane < k) cidx[lane] = a.idx[pos * a.kmax_list + lane];
+            } else {
+                pos = a.perm[first + l];
+                gidx = pos;
+                if (lane == 0) {
+                    uint64_t m = a.mask[pos];
+                    for (int i = 0; i < k; ++i) { cidx[i] = __builtin_ctzll(m); m &= m - 1; }
+                }
             }
+            __syncthreads();
+            const FactorOut<double> f = wave_factor(sR, N, cidx, k, sM, ks, sInv);
+            double sumlogd = 0.0;
+            if (a.write_H) sumlogd = wave_sum(lane < k ? sLogd[cidx[lane]] : 0.0);
+            if (lane == 0) {
+                // the wave engine is already FP64: never queue a refinement
+                EvalArgs b = a;
+                if (b.precision == THOI_FP32_REFINE) b.precision = THOI_FP64;
+                double om = 0.0;
+                const bool ok = store_result<double>(b, reduce, d, pos, k, f, sumlogd, sbias[0], sbias[1], sbias[2],
+                                                     true, om);
+                res_v[l - c0] = om;
+                res_g[l - c0] = gidx;
+                res_ok[l - c0] = ok;
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        const FactorOut<double> f = wave_factor(sR, N, cidx, k, sM, ks, sInv);
-        double sumlogd = 0.0;
-        if (a.write_H) sumlogd = wave_sum(lane < k ? sLogd[cidx[lane]] : 0.0);
-        if (lane == 0) {
-            // the wave engine is already FP64: never queue a refinement
-            EvalArgs b = a;
-            if (b.precision == THOI_FP32_REFINE) b.precision = THOI_FP64;
-            store_result<double>(b, d, pos, k, f, sumlogd, bt.dtc[k], bt.ddtc[k], bt.eta[k], true);
+        if constexpr (RED) {
+            const int i = lane;
+            const bool have = c0 + i < c1;
+            red_push(S, red, k, have && res_ok[i], have ? res_v[i] : 0.0, have ? res_g[i] : 0);
         }
-        __syncthreads();
     }
+    if constexpr (RED) red_end(S, red, a.hdr, d, k);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -326,7 +409,7 @@ struct RangeOrders {
 };
 
 template <int MODE>
-__global__ __launch_bounds__(64) void k_refine(EvalArgs a, RangeOrders ro, BiasTable bt, int kmax)
+__global__ __launch_bounds__(64) void k_refine(EvalArgs a, RangeOrders ro, RedArgs red, int kmax)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = a.N;
@@ -343,6 +426,7 @@ __global__ __launch_bounds__(64) void k_refine(EvalArgs a, RangeOrders ro, BiasT
     __syncthreads();
     const uint32_t n = min(a.hdr->refine_count, a.refine_cap);
     const int lane = threadIdx.x;
+    const bool reduce = red.active != 0;
     int staged = -1;
     for (uint32_t q = blockIdx.x; q < n; q += gridDim.x) {
         const int64_t o = a.refine_list[q];
@@ -377,11 +461,83 @@ __global__ __launch_bounds__(64) void k_refine(EvalArgs a, RangeOrders ro, BiasT
             EvalArgs b = a;
             b.precision = THOI_FP64;
             b.flags = nullptr;
-            store_result<double>(b, d, pos, k, f, sumlogd, bt.dtc[k], bt.ddtc[k], bt.eta[k], true);
-            if (a.flags) a.flags[o] = (uint8_t)(THOI_NPLET_REFINED | ((!f.ok || !isfinite(f.ld) || !isfinite(f.sa)) ? THOI_NPLET_NOT_PD : 0));
+            double dtc, ddtc, eta, om = 0.0;
+            bias_for(a.bias, k, dtc, ddtc, eta);
+            const bool ok = store_result<double>(b, reduce, d, pos, k, f, sumlogd, dtc, ddtc, eta, true, om);
+            if (a.flags) a.flags[o] = (uint8_t)(THOI_NPLET_REFINED | (ok ? 0 : THOI_NPLET_NOT_PD));
+            if (reduce && ok) {
+                const int64_t g = MODE == THOI_SEL_RANGE ? ro.g_begin + pos : pos;
+                red_late(red, a.hdr, d, k, g, om);
+            }
         }
         __syncthreads();
     }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Final merge of the streaming reduction: one workgroup per (order k, dataset d).
+// ------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_red_final(RedArgs red, WsHeader* hdr)
+{
+    __shared__ RedLds S;
+    const int k = blockIdx.x, d = blockIdx.y;
+    const int K = red.topk;
+    if (K <= 0) return;
+    double* tv = red.top_val + ((int64_t)d * (red.kmax + 1) + k) * 2 * K;
+    int64_t* tg = red.top_g + ((int64_t)d * (red.kmax + 1) + k) * 2 * K;
+    for (int i = threadIdx.x; i < 2 * K; i += blockDim.x) {
+        const int l = i / K, j = i % K;
+        const bool has = tg[i] >= 0;
+        S.key[l][0][j] = has ? red_list_key(l, tv[i]) : kKeyEmpty;
+        S.g[l][0][j] = has ? tg[i] : kGEmpty;
+    }
+    if (threadIdx.x == 0) { S.cur[0] = S.cur[1] = 0; }
+    __syncthreads();
+    const uint32_t nseg = min(hdr->seg_next, red.seg_cap);
+    for (uint32_t s = 0; s < nseg; ++s) {
+        const SegHdr h = red.seg_hdr[s];
+        if (h.d != d || h.k != k) continue;          // uniform
+        for (int l = 0; l < 2; ++l) {
+            const uint64_t* bk = red.seg_key + ((int64_t)s * 2 + l) * K;
+            const int64_t* bg = red.seg_g + ((int64_t)s * 2 + l) * K;
+            const int c = S.cur[l];
+            if (!red_less(bk[0], bg[0], S.key[l][c][K - 1], S.g[l][c][K - 1])) continue;   // uniform
+            red_merge_sorted(S, l, K, bk, bg, K);
+        }
+    }
+    const uint32_t nlate = min(hdr->late_next, red.late_cap);
+    for (uint32_t b0 = 0; b0 < nlate; b0 += blockDim.x) {
+        const uint32_t i = b0 + threadIdx.x;
+        bool mine = false;
+        double v = 0.0;
+        int64_t g = 0;
+        if (i < nlate) {
+            const LateEntry e = red.late[i];
+            mine = e.d == d && e.k == k;
+            v = e.v;
+            g = e.g;
+        }
+        red_offer(S, 0, K, mine, red_list_key(0, v), g);
+        red_offer(S, 1, K, mine, red_list_key(1, v), g);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * K; i += blockDim.x) {
+        const int l = i / K, j = i % K;
+        const uint64_t key = S.key[l][S.cur[l]][j];
+        const bool has = key != kKeyEmpty;
+        tv[i] = has ? red_list_val(l, key) : __builtin_nan("");
+        tg[i] = has ? S.g[l][S.cur[l]][j] : -1;
+    }
+}
+
+__global__ void k_red_init(double* top_val, int64_t* top_g, int64_t ntop, unsigned long long* hist, int64_t nhist)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ntop; i += stride) {
+        top_val[i] = __builtin_nan("");
+        top_g[i] = -1;
+    }
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nhist; i += stride) hist[i] = 0;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -394,7 +550,7 @@ __global__ void k_ws_clear(uint32_t* p, int64_t n)
 
 // grid ceil(B/256): order of every row (THOI_MAX_K + 1 = invalid) and per-order counts.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_list_classify(EvalArgs a, int64_t Bn, uint8_t* __restrict__ korder,
+__global__ __launch_bounds__(256) void k_list_classify(EvalArgs a, int reduce, int64_t Bn, uint8_t* __restrict__ korder,
                                                        unsigned long long* __restrict__ cnt)
 {
     __shared__ unsigned int h[kListOrders];
@@ -430,7 +586,7 @@ __global__ __launch_bounds__(256) void k_list_classify(EvalArgs a, int64_t Bn, u
             const int64_t plane = (int64_t)a.D * a.B;
             for (int d = 0; d < a.D; ++d) {
                 const int64_t o = (int64_t)d * a.B + b;
-                if (a.out) {
+                if (!reduce && a.out) {
                     for (int m = 0; m < 4 + a.write_H; ++m) {
                         if (a.out_f32) static_cast<float*>(a.out)[m * plane + o] = __builtin_nanf("");
                         else static_cast<double*>(a.out)[m * plane + o] = __builtin_nan("");
@@ -449,9 +605,10 @@ __global__ __launch_bounds__(256) void k_list_classify(EvalArgs a, int64_t Bn, u
 
 struct ClassMap { int8_t cls[kListOrders]; int8_t wave[kListOrders]; };
 
-// 1 workgroup: per-order base in perm, and first tile of each order inside its launch class.
+// 1 workgroup: per-order base in perm, and first workgroup of each order inside its launch.
 __global__ void k_list_scan(const unsigned long long* __restrict__ cnt, int64_t* __restrict__ base,
-                            int64_t* __restrict__ tile0, unsigned long long* __restrict__ cursor, ClassMap cm)
+                            int64_t* __restrict__ blk0, unsigned long long* __restrict__ cursor, ClassMap cm,
+                            int64_t per_lane_blk, int64_t per_wave_blk)
 {
     if (threadIdx.x != 0) return;
     int64_t b = 0;
@@ -462,14 +619,14 @@ __global__ void k_list_scan(const unsigned long long* __restrict__ cnt, int64_t*
         cursor[k] = 0;
         const int64_t c = (int64_t)cnt[k];
         b += c;
-        if (k > THOI_MAX_K) { tile0[k] = 0; continue; }
+        if (k > THOI_MAX_K) { blk0[k] = 0; continue; }
         if (cm.wave[k]) {
-            tile0[k] = wt;
-            wt += (c + kWaveTile - 1) / kWaveTile;
+            blk0[k] = wt;
+            wt += (c + per_wave_blk - 1) / per_wave_blk;
         } else {
             const int cl = cm.cls[k];
-            tile0[k] = ct[cl];
-            ct[cl] += (c + kTile - 1) / kTile;
+            blk0[k] = ct[cl];
+            ct[cl] += (c + per_lane_blk - 1) / per_lane_blk;
         }
     }
 }
@@ -501,17 +658,115 @@ __global__ __launch_bounds__(256) void k_list_scatter(int64_t Bn, const uint8_t*
 // ------------------------------------------------------------------------------------------------
 // Host side
 // ------------------------------------------------------------------------------------------------
-struct EvalWs {
-    size_t refine_off, korder_off, cnt_off, base_off, tile0_off, cursor_off, perm_off, total;
-    uint32_t refine_cap;
-};
-
 int64_t sel_B(const thoi_nplets* sel) { return sel->mode == THOI_SEL_RANGE ? sel->g_count : sel->B; }
 
-EvalWs eval_layout(int64_t D, const thoi_nplets* sel, const thoi_eval_opts* opts)
+int sel_kmax(const thoi_nplets* sel, int N)
+{
+    if (sel->mode == THOI_SEL_RANGE) return sel->kmax;
+    if (sel->mode == THOI_SEL_LIST) return sel->kmax_list < THOI_MAX_K ? sel->kmax_list : THOI_MAX_K;
+    return N < THOI_MAX_K ? N : THOI_MAX_K;
+}
+
+template <typename F>
+const KClass* classes_for(int& n)
+{
+    if constexpr (sizeof(F) == 4) { n = (int)(sizeof(kF32Classes) / sizeof(KClass)); return kF32Classes; }
+    n = (int)(sizeof(kF64Classes) / sizeof(KClass));
+    return kF64Classes;
+}
+
+int lane_max_for(int precision) { return precision == THOI_FP64 ? kF64LaneMax : kF32LaneMax; }
+
+template <typename F>
+int class_of(int k)
+{
+    int n = 0;
+    const KClass* cls = classes_for<F>(n);
+    int c = 0;
+    while (c < n - 1 && k > cls[c].hi) ++c;
+    return c;
+}
+
+// Launch plan of a call: workgroups per class and per wave launch; exact for RANGE, an upper
+// bound for LIST / MASK.
+struct Plan {
+    int ncls;
+    PieceTable tabs[8];
+    int64_t nblk[8];
+    PieceTable wtab;
+    int64_t wblk;
+    int wkmax;
+    int seg_tiles, wave_tile;
+    int64_t seg_cap;
+};
+
+template <typename F>
+Plan make_plan(int N, const thoi_nplets* sel, bool reduce, int precision)
+{
+    Plan P{};
+    const KClass* cls = classes_for<F>(P.ncls);
+    const int lane_max = lane_max_for(precision);
+    const int64_t Bn = sel_B(sel);
+    P.wave_tile = reduce ? kWaveTileRed : kWaveTileOut;
+    // reduce mode: a workgroup walks a segment of tiles so that one launch has a few thousand
+    // workgroups and the number of segments to merge stays bounded
+    P.seg_tiles = 1;
+    if (reduce) {
+        const int64_t tiles = (Bn + kTile - 1) / kTile;
+        P.seg_tiles = (int)((tiles + 16383) / 16384);
+        if (P.seg_tiles < 1) P.seg_tiles = 1;
+    }
+    const int64_t per_blk = (int64_t)kTile * P.seg_tiles;
+    if (sel->mode == THOI_SEL_RANGE) {
+        int64_t g = 0;
+        const int64_t gb = sel->g_begin, ge = sel->g_begin + sel->g_count;
+        for (int k = sel->kmin; k <= sel->kmax; ++k) {
+            const int64_t ck = (int64_t)binom_u64(N, k);
+            const int64_t lo = gb > g ? gb : g, hi = ge < g + ck ? ge : g + ck;
+            if (hi > lo) {
+                Piece p{};
+                p.k = k;
+                p.first = lo - g;
+                p.pos0 = lo - gb;
+                p.cnt = hi - lo;
+                if (k <= lane_max) {
+                    const int c = class_of<F>(k);
+                    p.blk0 = P.nblk[c];
+                    P.nblk[c] += (p.cnt + per_blk - 1) / per_blk;
+                    P.tabs[c].p[P.tabs[c].n++] = p;
+                } else {
+                    p.blk0 = P.wblk;
+                    P.wblk += (p.cnt + P.wave_tile - 1) / P.wave_tile;
+                    P.wtab.p[P.wtab.n++] = p;
+                    P.wkmax = k > P.wkmax ? k : P.wkmax;
+                }
+            }
+            g += ck;
+        }
+    } else {
+        for (int c = 0; c < P.ncls; ++c) P.nblk[c] = (Bn + per_blk - 1) / per_blk + (cls[c].hi - cls[c].lo + 1);
+        const int kcap = sel_kmax(sel, N);
+        if (kcap > lane_max) {
+            P.wblk = (Bn + P.wave_tile - 1) / P.wave_tile + (kcap - lane_max);
+            P.wkmax = kcap;
+        }
+    }
+    P.seg_cap = P.wblk;
+    for (int c = 0; c < P.ncls; ++c) P.seg_cap += P.nblk[c];
+    return P;
+}
+
+struct EvalWs {
+    size_t refine_off, korder_off, cnt_off, base_off, blk0_off, cursor_off, perm_off;
+    size_t seg_key_off, seg_g_off, seg_hdr_off, late_off, total;
+    uint32_t refine_cap, seg_cap, late_cap;
+};
+
+EvalWs eval_layout(int64_t D, int32_t N, const thoi_nplets* sel, const thoi_eval_opts* opts)
 {
     EvalWs w{};
     const int64_t B = sel_B(sel);
+    const bool reduce = opts->reduce != nullptr;
     size_t off = kWsHeader;
     if (opts->precision == THOI_FP32_REFINE) {
         const int64_t want = D * B;
@@ -524,202 +779,150 @@ EvalWs eval_layout(int64_t D, const thoi_nplets* sel, const thoi_eval_opts* opts
         w.korder_off = off; off = align_up(off + (size_t)B, 256);
         w.cnt_off = off; off = align_up(off + kListOrders * 8, 256);
         w.base_off = off; off = align_up(off + kListOrders * 8, 256);
-        w.tile0_off = off; off = align_up(off + kListOrders * 8, 256);
+        w.blk0_off = off; off = align_up(off + kListOrders * 8, 256);
         w.cursor_off = off; off = align_up(off + kListOrders * 8, 256);
         w.perm_off = off; off = align_up(off + (size_t)B * 8, 256);
+    }
+    if (reduce && opts->reduce->topk > 0) {
+        const int K = opts->reduce->topk;
+        const Plan P = opts->precision == THOI_FP64 ? make_plan<double>(N, sel, true, opts->precision)
+                                                    : make_plan<float>(N, sel, true, opts->precision);
+        const int64_t segs = P.seg_cap * D;
+        w.seg_cap = (uint32_t)(segs > 0 ? segs : 1);
+        w.seg_key_off = off; off = align_up(off + (size_t)w.seg_cap * 2 * K * 8, 256);
+        w.seg_g_off = off; off = align_up(off + (size_t)w.seg_cap * 2 * K * 8, 256);
+        w.seg_hdr_off = off; off = align_up(off + (size_t)w.seg_cap * sizeof(SegHdr), 256);
+        w.late_cap = w.refine_cap;
+        if (w.late_cap) { w.late_off = off; off = align_up(off + (size_t)w.late_cap * sizeof(LateEntry), 256); }
     }
     w.total = off;
     return w;
 }
 
-template <typename F>
-const KClass* classes_for(int& n)
-{
-    if constexpr (sizeof(F) == 4) { n = (int)(sizeof(kF32Classes) / sizeof(KClass)); return kF32Classes; }
-    n = (int)(sizeof(kF64Classes) / sizeof(KClass));
-    return kF64Classes;
-}
+typedef void (*LaneKernel)(EvalArgs, PieceTable, RedArgs);
 
-typedef void (*LaneKernel)(EvalArgs, PieceTable, BiasTable);
-
-template <typename F, int MODE>
-LaneKernel lane_kernel(int cls)
+template <typename F, int MODE, bool RED>
+LaneKernel lane_kernel_r(int cls)
 {
     if constexpr (sizeof(F) == 4) {
         switch (cls) {
-            case 0: return k_eval_lane<F, 0, 8, MODE>;
-            case 1: return k_eval_lane<F, 9, 12, MODE>;
-            case 2: return k_eval_lane<F, 13, 16, MODE>;
-            case 3: return k_eval_lane<F, 17, 20, MODE>;
-            default: return k_eval_lane<F, 21, 24, MODE>;
+            case 0: return k_eval_lane<F, 0, 8, MODE, RED>;
+            case 1: return k_eval_lane<F, 9, 12, MODE, RED>;
+            case 2: return k_eval_lane<F, 13, 16, MODE, RED>;
+            case 3: return k_eval_lane<F, 17, 20, MODE, RED>;
+            default: return k_eval_lane<F, 21, 24, MODE, RED>;
         }
     } else {
         switch (cls) {
-            case 0: return k_eval_lane<F, 0, 6, MODE>;
-            case 1: return k_eval_lane<F, 7, 10, MODE>;
-            case 2: return k_eval_lane<F, 11, 14, MODE>;
-            default: return k_eval_lane<F, 15, 18, MODE>;
+            case 0: return k_eval_lane<F, 0, 6, MODE, RED>;
+            case 1: return k_eval_lane<F, 7, 10, MODE, RED>;
+            case 2: return k_eval_lane<F, 11, 14, MODE, RED>;
+            default: return k_eval_lane<F, 15, 18, MODE, RED>;
         }
     }
 }
 
-// Bias offsets for orders lo..hi at entries [k - lo].
-BiasTable make_bias(const thoi_eval_opts* o, int lo, int hi)
-{
-    BiasTable bt{};
-    for (int k = lo; k <= hi && k - lo <= THOI_MAX_K; ++k) {
-        double a = 0, b = 0, c = 0;
-        if (o->bias_correct && k + 2 <= o->T) bias_offsets(k, o->T, &a, &b, &c);
-        bt.dtc[k - lo] = a;
-        bt.ddtc[k - lo] = b;
-        bt.eta[k - lo] = c;
-    }
-    return bt;
-}
-
-template <typename F>
-int lane_max_for() { return sizeof(F) == 4 ? kF32LaneMax : kF64LaneMax; }
-
-template <typename F>
-int class_of(int k)
-{
-    int n = 0;
-    const KClass* cls = classes_for<F>(n);
-    int c = 0;
-    while (c < n - 1 && k > cls[c].hi) ++c;
-    return c;
-}
-
-// RANGE: split [g_begin, g_begin + g_count) into per-order pieces and launch each class once.
-template <typename F>
-void launch_range(const EvalArgs& a, const thoi_nplets* sel, const thoi_eval_opts* opts, hipStream_t s)
-{
-    int ncls = 0;
-    const KClass* cls = classes_for<F>(ncls);
-    const int lane_max = lane_max_for<F>();
-    const int N = a.N;
-    int64_t g = 0;
-    for (int k = 0; k < sel->kmin; ++k) (void)k;
-    const int64_t gb = sel->g_begin, ge = sel->g_begin + sel->g_count;
-    PieceTable tabs[8] = {};
-    PieceTable wtab{};
-    int64_t ntiles[8] = {0}, wtiles = 0;
-    int wkmax = 0;
-    for (int k = sel->kmin; k <= sel->kmax; ++k) {
-        const int64_t ck = (int64_t)binom_u64(N, k);
-        const int64_t lo = gb > g ? gb : g, hi = ge < g + ck ? ge : g + ck;
-        if (hi > lo) {
-            Piece p{};
-            p.k = k;
-            p.first = lo - g;
-            p.pos0 = lo - gb;
-            p.cnt = hi - lo;
-            if (k <= lane_max) {
-                const int c = class_of<F>(k);
-                p.tile0 = ntiles[c];
-                ntiles[c] += (p.cnt + kTile - 1) / kTile;
-                tabs[c].p[tabs[c].n++] = p;
-            } else {
-                p.tile0 = wtiles;
-                wtiles += (p.cnt + kWaveTile - 1) / kWaveTile;
-                wtab.p[wtab.n++] = p;
-                wkmax = k > wkmax ? k : wkmax;
-            }
-        }
-        g += ck;
-    }
-    for (int c = 0; c < ncls; ++c) {
-        if (tabs[c].n == 0) continue;
-        const BiasTable bt = make_bias(opts, cls[c].lo, cls[c].hi);
-        const size_t lds = lane_lds_bytes(N, cls[c].hi, sizeof(F));
-        dim3 grid((unsigned)ntiles[c], (unsigned)a.D);
-        const LaneKernel kern = lane_kernel<F, THOI_SEL_RANGE>(c);
-        hipLaunchKernelGGL(kern, grid, dim3(kTile), lds, s, a, tabs[c], bt);
-    }
-    if (wtab.n) {
-        const BiasTable bt = make_bias(opts, 0, THOI_MAX_K);
-        dim3 grid((unsigned)wtiles, (unsigned)a.D);
-        hipLaunchKernelGGL(k_eval_wave<THOI_SEL_RANGE>, grid, dim3(64), wave_lds_bytes(N, wkmax, true), s, a, wtab, bt, 0, wkmax);
-    }
-}
-
-// LIST / MASK: bucket rows by order on the device, then launch every class with an upper-bound grid.
 template <typename F, int MODE>
-void launch_list(EvalArgs& a, const thoi_eval_opts* opts, const EvalWs& w, char* base, int64_t Bn, hipStream_t s)
+LaneKernel lane_kernel(int cls, bool reduce)
+{
+    return reduce ? lane_kernel_r<F, MODE, true>(cls) : lane_kernel_r<F, MODE, false>(cls);
+}
+
+typedef void (*WaveKernel)(EvalArgs, PieceTable, RedArgs, int, int);
+
+template <int MODE>
+WaveKernel wave_kernel(bool reduce)
+{
+    return reduce ? k_eval_wave<MODE, true> : k_eval_wave<MODE, false>;
+}
+
+size_t red_lds(bool reduce) { return reduce ? sizeof(RedLds) : 0; }
+
+template <typename F, int MODE>
+void launch_engines(EvalArgs& a, const Plan& P, const RedArgs& red, hipStream_t s)
 {
     int ncls = 0;
     const KClass* cls = classes_for<F>(ncls);
-    const int lane_max = lane_max_for<F>();
+    const bool reduce = red.active != 0;
+    const int N = a.N;
+    for (int c = 0; c < ncls; ++c) {
+        if (P.nblk[c] == 0) continue;
+        const int kb = MODE == THOI_SEL_RANGE ? cls[c].hi : 0;
+        const size_t lds = lane_stage_bytes(N, kb, sizeof(F)) + red_lds(reduce);
+        const LaneKernel kern = lane_kernel<F, MODE>(c, reduce);
+        hipLaunchKernelGGL(kern, dim3((unsigned)P.nblk[c], (unsigned)a.D), dim3(kTile), lds, s, a, P.tabs[c], red);
+    }
+    if (P.wblk) {
+        const int klo = MODE == THOI_SEL_RANGE ? 0 : lane_max_for(a.precision) + 1;
+        const size_t lds = wave_stage_bytes(N, P.wkmax, MODE == THOI_SEL_RANGE) + red_lds(reduce);
+        const WaveKernel wk = wave_kernel<MODE>(reduce);
+        hipLaunchKernelGGL(wk, dim3((unsigned)P.wblk, (unsigned)a.D), dim3(64), lds, s, a, P.wtab, red, klo, P.wkmax);
+    }
+}
+
+template <typename F, int MODE>
+void launch_list(EvalArgs& a, const Plan& P, const RedArgs& red, const EvalWs& w, char* base, int64_t Bn,
+                 hipStream_t s)
+{
+    const int lane_max = lane_max_for(a.precision);
     uint8_t* korder = reinterpret_cast<uint8_t*>(base + w.korder_off);
     unsigned long long* cnt = reinterpret_cast<unsigned long long*>(base + w.cnt_off);
     int64_t* lbase = reinterpret_cast<int64_t*>(base + w.base_off);
-    int64_t* ltile0 = reinterpret_cast<int64_t*>(base + w.tile0_off);
+    int64_t* lblk0 = reinterpret_cast<int64_t*>(base + w.blk0_off);
     unsigned long long* cursor = reinterpret_cast<unsigned long long*>(base + w.cursor_off);
     int64_t* perm = reinterpret_cast<int64_t*>(base + w.perm_off);
     a.perm = perm;
     a.lcnt = reinterpret_cast<const int64_t*>(cnt);
     a.lbase = lbase;
-    a.ltile0 = ltile0;
+    a.lblk0 = lblk0;
 
     hipLaunchKernelGGL(k_ws_clear, dim3(1), dim3(256), 0, s, reinterpret_cast<uint32_t*>(cnt), (int64_t)kListOrders * 2);
     const unsigned nb = (unsigned)((Bn + 255) / 256);
-    if (Bn > 0) hipLaunchKernelGGL(k_list_classify<MODE>, dim3(nb), dim3(256), 0, s, a, Bn, korder, cnt);
+    hipLaunchKernelGGL(k_list_classify<MODE>, dim3(nb), dim3(256), 0, s, a, red.active, Bn, korder, cnt);
     ClassMap cm{};
     for (int k = 0; k < kListOrders; ++k) {
         cm.wave[k] = (k > lane_max) ? 1 : 0;
         cm.cls[k] = (int8_t)class_of<F>(k <= lane_max ? k : lane_max);
     }
-    hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(64), 0, s, cnt, lbase, ltile0, cursor, cm);
-    if (Bn == 0) return;
+    hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(64), 0, s, cnt, lbase, lblk0, cursor, cm,
+                       (int64_t)kTile * P.seg_tiles, (int64_t)P.wave_tile);
     hipLaunchKernelGGL(k_list_scatter, dim3(nb), dim3(256), 0, s, Bn, korder, lbase, cursor, perm);
-
-    const int N = a.N;
-    PieceTable none{};
-    for (int c = 0; c < ncls; ++c) {
-        const BiasTable bt = make_bias(opts, cls[c].lo, cls[c].hi);
-        const size_t lds = lane_lds_bytes(N, 0, sizeof(F));
-        const int64_t grid_x = (Bn + kTile - 1) / kTile + (cls[c].hi - cls[c].lo + 1);
-        const LaneKernel kern = lane_kernel<F, MODE>(c);
-        hipLaunchKernelGGL(kern, dim3((unsigned)grid_x, (unsigned)a.D), dim3(kTile), lds, s, a, none, bt);
-    }
-    const int kcap = MODE == THOI_SEL_LIST ? a.kmax_list : (N < 64 ? N : 64);
-    if (kcap > lane_max) {
-        const BiasTable bt = make_bias(opts, 0, THOI_MAX_K);
-        const int64_t grid_x = (Bn + kWaveTile - 1) / kWaveTile + (kcap - lane_max);
-        hipLaunchKernelGGL(k_eval_wave<MODE>, dim3((unsigned)grid_x, (unsigned)a.D), dim3(64),
-                           wave_lds_bytes(N, kcap, false), s, a, none, bt, lane_max + 1, kcap);
-    }
+    launch_engines<F, MODE>(a, P, red, s);
 }
 
 template <typename F>
-void launch_forward(EvalArgs& a, const thoi_nplets* sel, const thoi_eval_opts* opts, const EvalWs& w, char* base,
-                    hipStream_t s)
+void launch_forward(EvalArgs& a, const thoi_nplets* sel, const Plan& P, const RedArgs& red, const EvalWs& w,
+                    char* base, hipStream_t s)
 {
     const int64_t Bn = sel_B(sel);
-    if (sel->mode == THOI_SEL_RANGE) launch_range<F>(a, sel, opts, s);
-    else if (sel->mode == THOI_SEL_LIST) launch_list<F, THOI_SEL_LIST>(a, opts, w, base, Bn, s);
-    else launch_list<F, THOI_SEL_MASK>(a, opts, w, base, Bn, s);
+    if (sel->mode == THOI_SEL_RANGE) launch_engines<F, THOI_SEL_RANGE>(a, P, red, s);
+    else if (sel->mode == THOI_SEL_LIST) launch_list<F, THOI_SEL_LIST>(a, P, red, w, base, Bn, s);
+    else launch_list<F, THOI_SEL_MASK>(a, P, red, w, base, Bn, s);
 }
 
 }  // namespace
 
 size_t eval_ws_bytes(int64_t D, int32_t N, const thoi_nplets* sel, const thoi_eval_opts* opts)
 {
-    (void)N;
-    return eval_layout(D, sel, opts).total;
+    return eval_layout(D, N, sel, opts).total;
 }
 
 // Largest LDS footprint any kernel of this call needs (the host rejects calls above the limit).
 size_t eval_lds_bytes(int32_t N, const thoi_nplets* sel, const thoi_eval_opts* opts)
 {
     const bool range = sel->mode == THOI_SEL_RANGE;
-    const int kmax = range ? sel->kmax : (sel->mode == THOI_SEL_LIST ? sel->kmax_list : (N < 64 ? N : 64));
+    const bool reduce = opts->reduce != nullptr;
+    const int kmax = sel_kmax(sel, N);
     const int fsize = opts->precision == THOI_FP64 ? 8 : 4;
-    const int lane_max = opts->precision == THOI_FP64 ? kF64LaneMax : kF32LaneMax;
-    size_t need = lane_lds_bytes(N, range ? kF32LaneMax : 0, fsize);   // kb <= largest class bound
-    if (kmax > lane_max || opts->precision == THOI_FP32_REFINE) {
-        const size_t w = wave_lds_bytes(N, kmax < 64 ? kmax : 64, range);
+    const int lane_max = lane_max_for(opts->precision);
+    size_t need = lane_stage_bytes(N, range ? kF32LaneMax : 0, fsize) + red_lds(reduce);
+    if (kmax > lane_max) {
+        const size_t w = wave_stage_bytes(N, kmax, range) + red_lds(reduce);
         need = need > w ? need : w;
+    }
+    if (opts->precision == THOI_FP32_REFINE) {
+        const size_t r = wave_stage_bytes(N, kmax, range);
+        need = need > r ? need : r;
     }
     return need;
 }
@@ -727,37 +930,74 @@ size_t eval_lds_bytes(int32_t N, const thoi_nplets* sel, const thoi_eval_opts* o
 thoi_status launch_eval(const double* Sigma, int64_t D, int32_t N, const thoi_nplets* sel, const thoi_eval_opts* opts,
                         void* out, uint8_t* flags, void* ws, size_t ws_bytes, hipStream_t s)
 {
-    const EvalWs w = eval_layout(D, sel, opts);
+    const EvalWs w = eval_layout(D, N, sel, opts);
     if (ws == nullptr || ws_bytes < w.total) return THOI_EWORKSPACE;
     char* base = static_cast<char*>(ws);
+    const bool reduce = opts->reduce != nullptr;
     EvalArgs a{};
     a.Sigma = Sigma;
     a.N = N;
     a.D = (int32_t)D;
     a.B = sel_B(sel);
+    a.g_begin = sel->mode == THOI_SEL_RANGE ? sel->g_begin : 0;
     a.out = out;
     a.out_f32 = opts->out_dtype == THOI_DTYPE_F32;
-    a.write_H = opts->write_entropy ? 1 : 0;
+    a.write_H = (opts->write_entropy && !reduce) ? 1 : 0;
     a.flags = flags;
     a.precision = opts->precision;
     a.vif_tau = (float)(opts->vif_tau > 0 ? opts->vif_tau : 1e3);
     a.hdr = reinterpret_cast<WsHeader*>(base);
     a.refine_list = opts->precision == THOI_FP32_REFINE ? reinterpret_cast<int64_t*>(base + w.refine_off) : nullptr;
     a.refine_cap = w.refine_cap;
-    a.bias = opts->bias_correct;
+    a.bias.on = opts->bias_correct ? 1 : 0;
+    a.bias.T = opts->T;
+    if (opts->bias_correct) bias_psi_seeds(opts->T, &a.bias.psi1, &a.bias.psi2);
     a.idx = sel->idx;
     a.kmax_list = sel->kmax_list;
     a.mask = sel->mask;
 
+    RedArgs red{};
+    const int kmax = sel_kmax(sel, N);
+    if (reduce) {
+        const thoi_reduce* r = opts->reduce;
+        red.active = 1;
+        red.topk = r->topk;
+        red.bins = r->hist_bins;
+        red.kmax = kmax;
+        red.top_val = r->top_val;
+        red.top_g = r->top_g;
+        red.hist = reinterpret_cast<unsigned long long*>(r->hist);
+        red.seg_key = reinterpret_cast<uint64_t*>(base + w.seg_key_off);
+        red.seg_g = reinterpret_cast<int64_t*>(base + w.seg_g_off);
+        red.seg_hdr = reinterpret_cast<SegHdr*>(base + w.seg_hdr_off);
+        red.seg_next = &a.hdr->seg_next;
+        red.seg_cap = w.seg_cap;
+        red.late = w.late_cap ? reinterpret_cast<LateEntry*>(base + w.late_off) : nullptr;
+        red.late_next = &a.hdr->late_next;
+        red.late_cap = w.late_cap;
+        for (int k = 0; k <= kmax; ++k) {
+            red.lo[k] = r->hist_bins ? r->hist_lo_hi[2 * k] : 0.0;
+            red.hi[k] = r->hist_bins ? r->hist_lo_hi[2 * k + 1] : 1.0;
+        }
+    }
+
     hipLaunchKernelGGL(k_ws_clear, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t*>(base), (int64_t)(kWsHeader / 4));
     if (D == 0 || a.B == 0) return hip_status(hipGetLastError());
 
-    if (opts->precision == THOI_FP64) launch_forward<double>(a, sel, opts, w, base, s);
-    else launch_forward<float>(a, sel, opts, w, base, s);
+    if (opts->precision == THOI_FP64) {
+        const Plan P = make_plan<double>(N, sel, reduce, opts->precision);
+        a.seg_tiles = P.seg_tiles;
+        a.wave_tile = P.wave_tile;
+        launch_forward<double>(a, sel, P, red, w, base, s);
+    } else {
+        const Plan P = make_plan<float>(N, sel, reduce, opts->precision);
+        a.seg_tiles = P.seg_tiles;
+        a.wave_tile = P.wave_tile;
+        launch_forward<float>(a, sel, P, red, w, base, s);
+    }
 
     if (opts->precision == THOI_FP32_REFINE) {
         RangeOrders ro{};
-        int kmax = THOI_MAX_K;
         if (sel->mode == THOI_SEL_RANGE) {
             ro.kmin = sel->kmin;
             ro.kmax = sel->kmax;
@@ -767,22 +1007,28 @@ thoi_status launch_eval(const double* Sigma, int64_t D, int32_t N, const thoi_np
                 ro.ostart[k] = g;
                 if (k <= sel->kmax) g += (int64_t)binom_u64(N, k);
             }
-            kmax = sel->kmax;
-        } else if (sel->mode == THOI_SEL_LIST) {
-            kmax = sel->kmax_list < THOI_MAX_K ? sel->kmax_list : THOI_MAX_K;
-        } else {
-            kmax = N < THOI_MAX_K ? N : THOI_MAX_K;
         }
-        const BiasTable bt = make_bias(opts, 0, THOI_MAX_K);
-        const size_t lds = wave_lds_bytes(N, kmax, sel->mode == THOI_SEL_RANGE);
+        const size_t lds = wave_stage_bytes(N, kmax, sel->mode == THOI_SEL_RANGE);
         const unsigned G = 1024;
         if (sel->mode == THOI_SEL_RANGE)
-            hipLaunchKernelGGL(k_refine<THOI_SEL_RANGE>, dim3(G), dim3(64), lds, s, a, ro, bt, kmax);
+            hipLaunchKernelGGL(k_refine<THOI_SEL_RANGE>, dim3(G), dim3(64), lds, s, a, ro, red, kmax);
         else if (sel->mode == THOI_SEL_LIST)
-            hipLaunchKernelGGL(k_refine<THOI_SEL_LIST>, dim3(G), dim3(64), lds, s, a, ro, bt, kmax);
+            hipLaunchKernelGGL(k_refine<THOI_SEL_LIST>, dim3(G), dim3(64), lds, s, a, ro, red, kmax);
         else
-            hipLaunchKernelGGL(k_refine<THOI_SEL_MASK>, dim3(G), dim3(64), lds, s, a, ro, bt, kmax);
+            hipLaunchKernelGGL(k_refine<THOI_SEL_MASK>, dim3(G), dim3(64), lds, s, a, ro, red, kmax);
     }
+    if (reduce && red.topk > 0)
+        hipLaunchKernelGGL(k_red_final, dim3((unsigned)(kmax + 1), (unsigned)D), dim3(256), 0, s, red, a.hdr);
+    return hip_status(hipGetLastError());
+}
+
+thoi_status launch_reduce_init(const thoi_reduce* red, int64_t D, int32_t kmax, hipStream_t s)
+{
+    const int64_t ntop = red->topk > 0 ? D * (kmax + 1) * 2 * red->topk : 0;
+    const int64_t nhist = red->hist_bins > 0 ? D * (kmax + 1) * (red->hist_bins + 2) : 0;
+    if (ntop + nhist == 0) return THOI_OK;
+    hipLaunchKernelGGL(k_red_init, dim3(256), dim3(256), 0, s, red->top_val, red->top_g, ntop,
+                       reinterpret_cast<unsigned long long*>(red->hist), nhist);
     return hip_status(hipGetLastError());
 }
 

@@ -14,8 +14,8 @@ namespace thoi {
 struct WsHeader {
     int32_t status;          // THOI_OK or a thoi_status raised on the device
     uint32_t refine_count;   // FP32_REFINE: number of n-plets appended to the refine list
-    uint32_t refine_cap;     // capacity of the refine list
-    uint32_t pad0;
+    uint32_t seg_next;       // streaming reduction: segments written
+    uint32_t late_next;      // streaming reduction: FP64-refined values queued
     uint64_t reserved[30];
 };
 static_assert(sizeof(WsHeader) == 256, "workspace header is 256 bytes");
@@ -37,6 +37,8 @@ thoi_status hip_status(hipError_t e);
 uint64_t binom_u64(int n, int m);
 // Bias offsets of order k (see thoi_bias_offsets).
 void bias_offsets(int k, int T, double* d_tc, double* d_dtc, double* eta);
+// psi((T-1)/2) and psi((T-2)/2), the seeds of the device-side recurrence for the offsets.
+void bias_psi_seeds(int T, double* psi1, double* psi2);
 
 // Launchers implemented in the kernel translation units.
 thoi_status launch_copulize(const double* X, int64_t D, int64_t T, int64_t N, int32_t z_dtype, void* Z,
