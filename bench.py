@@ -42,6 +42,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the CPU oracle sample")
     p.add_argument("--skip-fp64", action="store_true")
+    p.add_argument("--profile-kernels", action="store_true",
+                   help="only run a 256 MiB device copy and the dominant evaluation launch 3 times each "
+                        "(for hardware-counter runs), then exit")
     return p.parse_args()
 
 
@@ -156,6 +159,21 @@ def main():
     X = torch.from_numpy(synth.latent_20()[None]).to(dev)
     total = B.thoi_count(N, kmin, kmax)
     use_graph = not args.no_graph
+
+    if args.profile_kernels:
+        # calibration: a plain copy of known size, then the dominant evaluation launch
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)      # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        st = Step(torch, B, api, X, "fp32", 9, 12)
+        st(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        for _ in range(2):
+            st.evaluate(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_kernels": True, "copy_bytes_each_way": src.numel() * 4,
+                          "dominant_nplets": sum(math.comb(N, k) for k in range(9, 13))}), flush=True)
+        return
 
     # ------------------------------------------------------------------ FP32 + FP64 refinement (the metric)
     s32 = Step(torch, B, api, X, "fp32_refine", kmin, kmax)

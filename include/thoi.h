@@ -127,6 +127,8 @@ typedef struct {
     int32_t T;                   /* samples per dataset (bias correction only)                  */
     int32_t write_entropy;       /* 1: a fifth output plane with H(X^n)                          */
     const thoi_reduce* reduce;   /* host; NULL = write the full output planes                    */
+    int32_t seg_tiles;           /* tuning: tiles of 256 n-plets per workgroup; 0 = library choice */
+    int32_t grid_blocks;         /* tuning: workgroups of a persistent launch; 0 = library choice  */
 } thoi_eval_opts;
 
 /*
@@ -180,6 +182,32 @@ thoi_status thoi_nplets_eval(const double* Sigma, int64_t D, int32_t N, const th
 thoi_status thoi_nplets_eval_backward(const double* Sigma, int64_t D, int32_t N, const thoi_nplets* sel,
                                       const thoi_eval_opts* opts, const float* grad_out,
                                       float* grad_Sigma, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Many datasets of uneven size in one call (Methods, "Parallel and batched computation of HOI":
+ * several datasets; here each with its own number of variables and samples): every n-plet of
+ * orders kmin..kmax of every dataset.
+ *   Sigma: device, the D matrices back to back; matrix d is [N_d][N_d] FP64 and starts at
+ *          element sum_{e<d} N_e^2.
+ *   N_d: host [D], 1 <= N_d <= THOI_MAX_N_RANGE.  T_d: host [D] sample counts, needed only with
+ *        bias correction (opts->T is ignored), else may be NULL.
+ *   Output position of the b-th n-plet of dataset d (in that dataset's RANGE order) is
+ *   out_off[d] + b, out_off being the exclusive prefix sum of thoi_count(N_d, kmin, kmax)
+ *   (thoi_multi_offsets); out: device [P][total] (P = 4, or 5 with write_entropy); flags:
+ *   device [total] or NULL.  With opts->reduce the reducer arrays are [D][kmax+1]... as in
+ *   thoi_nplets_eval and g is the index inside dataset d.
+ *   kmax must not exceed the register-resident orders (24 in FP32, 18 in FP64).
+ * Work runs as one persistent launch per register class over a (dataset, order, tile) table
+ * that a planning kernel builds in the workspace; datasets are processed in chunks of 256.
+ */
+thoi_status thoi_nplets_eval_multi(const double* Sigma, const int32_t* N_d, const int32_t* T_d, int64_t D,
+                                   int32_t kmin, int32_t kmax, const thoi_eval_opts* opts, void* out,
+                                   uint8_t* flags, void* ws, size_t ws_bytes, void* stream);
+/* Host, pure: out_off[0..D] (exclusive prefix sums of per-dataset n-plet counts, out_off[D] = total). */
+thoi_status thoi_multi_offsets(const int32_t* N_d, int64_t D, int32_t kmin, int32_t kmax, int64_t* out_off);
+/* Device workspace bytes for thoi_nplets_eval_multi. */
+size_t thoi_multi_workspace_bytes(const int32_t* N_d, int64_t D, int32_t kmin, int32_t kmax,
+                                  const thoi_eval_opts* opts);
 
 /* Initialise reducer arrays for D datasets (top_g = -1, hist = 0). */
 thoi_status thoi_reduce_init(const thoi_reduce* red, int64_t D, int32_t kmax, void* stream);

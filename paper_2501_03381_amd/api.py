@@ -117,10 +117,11 @@ def _n_out(sel: B.ThoiNplets) -> int:
 
 
 def make_opts(precision: str = "fp32_refine", out_dtype: torch.dtype = torch.float32, vif_tau: float = 1e3,
-              bias_correct: bool = False, T: int = 0, write_entropy: bool = False) -> B.ThoiEvalOpts:
+              bias_correct: bool = False, T: int = 0, write_entropy: bool = False, seg_tiles: int = 0,
+              grid_blocks: int = 0) -> B.ThoiEvalOpts:
     return B.ThoiEvalOpts(precision=_PREC[precision], out_dtype=_DT[out_dtype], vif_tau=float(vif_tau),
                           bias_correct=int(bool(bias_correct)), T=int(T), write_entropy=int(bool(write_entropy)),
-                          reduce=None)
+                          reduce=None, seg_tiles=int(seg_tiles), grid_blocks=int(grid_blocks))
 
 
 # ------------------------------------------------------------------------------------------------ evaluation
@@ -198,6 +199,64 @@ def nplets_measures(Sigma: torch.Tensor, *, orders: tuple[int, int] | None = Non
     if Sigma.dim() == 2:
         return out[:, 0], flags[0]
     return out, flags
+
+
+# ------------------------------------------------------------------------------------------------ uneven datasets
+def pack_covariances(Sigmas) -> tuple[torch.Tensor, list[int]]:
+    """Concatenate square float64 device matrices of different sizes (the multi-dataset layout)."""
+    Ns = [int(S.shape[0]) for S in Sigmas]
+    flat = torch.cat([S.contiguous().reshape(-1) for S in Sigmas]) if Sigmas else torch.empty(0, dtype=torch.float64)
+    return flat, Ns
+
+
+class MultiEvaluator:
+    """All n-plets of orders kmin..kmax of D datasets of uneven size, one persistent launch per
+    register class (thoi_nplets_eval_multi).  Output [P, total]; dataset d is the slice
+    offsets[d]:offsets[d+1]."""
+
+    def __init__(self, N_d, kmin: int, kmax: int, device, precision: str = "fp32_refine",
+                 out_dtype: torch.dtype = torch.float32, T_d=None, bias_correct: bool = False,
+                 write_entropy: bool = False, seg_tiles: int = 0, grid_blocks: int = 0, reduce_state=None):
+        import numpy as np
+        self.N_d = np.ascontiguousarray(N_d, dtype=np.int32)
+        self.T_d = None if T_d is None else np.ascontiguousarray(T_d, dtype=np.int32)
+        self.D, self.kmin, self.kmax = len(self.N_d), kmin, kmax
+        self.offsets = B.thoi_multi_offsets(self.N_d, kmin, kmax)
+        self.total = int(self.offsets[-1])
+        self.opts = make_opts(precision, out_dtype, 1e3, bias_correct, 0, write_entropy, seg_tiles, grid_blocks)
+        self.reduce_state = reduce_state
+        if reduce_state is not None:
+            self.opts.reduce = ctypes.pointer(reduce_state.struct)
+        planes = 5 if write_entropy else 4
+        self.out = None if reduce_state is not None else torch.empty((planes, self.total), dtype=out_dtype,
+                                                                      device=device)
+        self.flags = torch.empty(self.total, dtype=torch.uint8, device=device)
+        nb = B.thoi_multi_workspace_bytes(self.N_d.ctypes.data_as(ctypes.c_void_p), self.D, kmin, kmax, self.opts)
+        self.ws = _workspace(nb, device)
+        self.device = device
+
+    def __call__(self, Sigma_packed: torch.Tensor, stream=None):
+        st = ctypes.c_void_p(stream) if stream is not None else _stream(self.device)
+        Tp = self.T_d.ctypes.data_as(ctypes.c_void_p) if self.T_d is not None else None
+        B.thoi_nplets_eval_multi(_ptr(Sigma_packed), self.N_d.ctypes.data_as(ctypes.c_void_p), Tp, self.D, self.kmin,
+                                 self.kmax, self.opts, _ptr(self.out), _ptr(self.flags), _ptr(self.ws),
+                                 self.ws.numel(), st)
+        return self.out, self.flags
+
+    def status(self) -> int:
+        return device_status(self.ws)
+
+
+def nplets_measures_multi(Sigmas, kmin: int, kmax: int, *, precision: str = "fp32_refine",
+                          out_dtype: torch.dtype = torch.float32, T_d=None, bias_correct: bool = False,
+                          write_entropy: bool = False, check: bool = True):
+    """(out [P, total], flags [total], offsets [D+1]) for a list of float64 [N_d, N_d] device matrices."""
+    flat, Ns = pack_covariances(Sigmas)
+    ev = MultiEvaluator(Ns, kmin, kmax, flat.device, precision, out_dtype, T_d, bias_correct, write_entropy)
+    out, flags = ev(flat)
+    if check:
+        raise_on_device_status(ev.ws, "thoi_nplets_eval_multi")
+    return out, flags, ev.offsets
 
 
 # ------------------------------------------------------------------------------------------------ streaming reduction

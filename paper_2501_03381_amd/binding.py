@@ -31,7 +31,8 @@ THOI_MAX_K = 64
 EXPORTS = [
     "thoi_copulize", "thoi_cov", "thoi_nplets_eval", "thoi_nplets_eval_backward", "thoi_reduce_init",
     "thoi_workspace_bytes", "thoi_ws_status_offset", "thoi_count", "thoi_unrank_host", "thoi_bias_offsets",
-    "thoi_status_string", "thoi_version",
+    "thoi_status_string", "thoi_version", "thoi_nplets_eval_multi", "thoi_multi_offsets",
+    "thoi_multi_workspace_bytes",
 ]
 
 
@@ -69,6 +70,8 @@ class ThoiEvalOpts(ctypes.Structure):
         ("T", ctypes.c_int32),
         ("write_entropy", ctypes.c_int32),
         ("reduce", ctypes.POINTER(ThoiReduce)),
+        ("seg_tiles", ctypes.c_int32),
+        ("grid_blocks", ctypes.c_int32),
     ]
 
 
@@ -107,10 +110,14 @@ def lib():
                                     ctypes.POINTER(ctypes.c_double)]
     L.thoi_status_string.argtypes = [I32]
     L.thoi_status_string.restype = ctypes.c_char_p
+    L.thoi_nplets_eval_multi.argtypes = [P, P, P, I64, I32, I32, OP, P, P, P, SZ, P]
+    L.thoi_multi_offsets.argtypes = [P, I64, I32, I32, P]
+    L.thoi_multi_workspace_bytes.argtypes = [P, I64, I32, I32, OP]
+    L.thoi_multi_workspace_bytes.restype = SZ
     L.thoi_version.argtypes = []
     L.thoi_version.restype = ctypes.c_char_p
     for fn in ("thoi_copulize", "thoi_cov", "thoi_nplets_eval", "thoi_nplets_eval_backward", "thoi_reduce_init",
-               "thoi_unrank_host", "thoi_bias_offsets"):
+               "thoi_unrank_host", "thoi_bias_offsets", "thoi_nplets_eval_multi", "thoi_multi_offsets"):
         getattr(L, fn).restype = I32
     _lib = L
     return L
@@ -144,6 +151,25 @@ def thoi_nplets_eval_backward(Sigma, D, N, sel: ThoiNplets, opts: ThoiEvalOpts, 
 
 def thoi_reduce_init(red: ThoiReduce, D, kmax, stream):
     check("thoi_reduce_init", lib().thoi_reduce_init(ctypes.byref(red), D, kmax, stream))
+
+
+def thoi_nplets_eval_multi(Sigma, N_d, T_d, D, kmin, kmax, opts: ThoiEvalOpts, out, flags, ws, ws_bytes, stream):
+    check("thoi_nplets_eval_multi", lib().thoi_nplets_eval_multi(Sigma, N_d, T_d, D, kmin, kmax, ctypes.byref(opts),
+                                                                 out, flags, ws, ws_bytes, stream))
+
+
+def thoi_multi_offsets(N_d, kmin: int, kmax: int):
+    """Host: exclusive prefix sums of per-dataset counts (length D + 1)."""
+    import numpy as np
+    Nd = np.ascontiguousarray(N_d, dtype=np.int32)
+    off = np.zeros(len(Nd) + 1, dtype=np.int64)
+    check("thoi_multi_offsets", lib().thoi_multi_offsets(Nd.ctypes.data_as(ctypes.c_void_p), len(Nd), kmin, kmax,
+                                                         off.ctypes.data_as(ctypes.c_void_p)))
+    return off
+
+
+def thoi_multi_workspace_bytes(N_d, D, kmin, kmax, opts: ThoiEvalOpts) -> int:
+    return int(lib().thoi_multi_workspace_bytes(N_d, D, kmin, kmax, ctypes.byref(opts)))
 
 
 def thoi_workspace_bytes(which, D, T, N, sel=None, opts=None) -> int:

@@ -228,6 +228,82 @@ thoi_status thoi_nplets_eval_backward(const double* Sigma, int64_t D, int32_t N,
     return launch_backward(Sigma, D, N, sel, opts, grad_out, grad_Sigma, ws, ws_bytes, (hipStream_t)stream);
 }
 
+static thoi_status check_multi(const int32_t* N_d, const int32_t* T_d, int64_t D, int32_t kmin, int32_t kmax,
+                               const thoi_eval_opts* opts, int64_t* total)
+{
+    if (!opts || D < 0 || (D > 0 && !N_d)) return THOI_EINVAL;
+    if (opts->precision != THOI_FP64 && opts->precision != THOI_FP32 && opts->precision != THOI_FP32_REFINE)
+        return THOI_EINVAL;
+    if (!valid_dtype(opts->out_dtype) || opts->seg_tiles < 0 || opts->grid_blocks < 0) return THOI_EINVAL;
+    if (opts->write_entropy != 0 && opts->write_entropy != 1) return THOI_EINVAL;
+    if (kmin < 0 || kmax < kmin) return THOI_EINVAL;
+    if (kmax > multi_lane_max(opts->precision) || opts->seg_tiles > 4096) return THOI_EUNSUPPORTED;
+    if (opts->bias_correct && !T_d) return THOI_EINVAL;
+    int nmax = 0;
+    int64_t s = 0;
+    for (int64_t d = 0; d < D; ++d) {
+        if (N_d[d] < 1) return THOI_EINVAL;
+        if (N_d[d] > THOI_MAX_N_RANGE) return THOI_EUNSUPPORTED;
+        if (opts->bias_correct && (T_d[d] < kmax + 2 || T_d[d] < 3)) return THOI_EINVAL;
+        nmax = N_d[d] > nmax ? N_d[d] : nmax;
+        const int64_t c = count_orders(N_d[d], kmin, kmax);
+        if (c < 0 || s > ((int64_t)1 << 42) - c) return THOI_EUNSUPPORTED;
+        s += c;
+    }
+    if (opts->reduce) {
+        const thoi_reduce* r = opts->reduce;
+        if (r->topk < 0 || r->hist_bins < 0 || (r->topk == 0 && r->hist_bins == 0)) return THOI_EINVAL;
+        if (r->topk > 256 || r->hist_bins > 4096) return THOI_EUNSUPPORTED;
+        if (r->topk > 0 && (!r->top_val || !r->top_g)) return THOI_EINVAL;
+        if (r->hist_bins > 0) {
+            if (!r->hist || !r->hist_lo_hi) return THOI_EINVAL;
+            for (int k = 0; k <= kmax; ++k) {
+                const double lo = r->hist_lo_hi[2 * k], hi = r->hist_lo_hi[2 * k + 1];
+                if (!(lo < hi) || !isfinite(lo) || !isfinite(hi)) return THOI_EINVAL;
+            }
+        }
+    }
+    if (D > 0 && multi_lds_bytes(nmax, kmax, opts) > kLdsLimit) return THOI_EUNSUPPORTED;
+    *total = s;
+    return THOI_OK;
+}
+
+thoi_status thoi_nplets_eval_multi(const double* Sigma, const int32_t* N_d, const int32_t* T_d, int64_t D,
+                                   int32_t kmin, int32_t kmax, const thoi_eval_opts* opts, void* out,
+                                   uint8_t* flags, void* ws, size_t ws_bytes, void* stream)
+{
+    int64_t total = 0;
+    const thoi_status st = check_multi(N_d, T_d, D, kmin, kmax, opts, &total);
+    if (st != THOI_OK) return st;
+    if (total > 0 && !Sigma) return THOI_EINVAL;
+    if (total > 0 && !opts->reduce && !out) return THOI_EINVAL;
+    if (total == 0) return THOI_OK;
+    return launch_multi(Sigma, N_d, T_d, D, kmin, kmax, opts, out, flags, ws, ws_bytes, (hipStream_t)stream);
+}
+
+thoi_status thoi_multi_offsets(const int32_t* N_d, int64_t D, int32_t kmin, int32_t kmax, int64_t* out_off)
+{
+    if (D < 0 || (D > 0 && !N_d) || !out_off || kmin < 0 || kmax < kmin) return THOI_EINVAL;
+    int64_t s = 0;
+    for (int64_t d = 0; d < D; ++d) {
+        if (N_d[d] < 1 || N_d[d] > 64) return THOI_EINVAL;
+        out_off[d] = s;
+        const int64_t c = count_orders(N_d[d], kmin, kmax);
+        if (c < 0) return THOI_EUNSUPPORTED;
+        s += c;
+    }
+    out_off[D] = s;
+    return THOI_OK;
+}
+
+size_t thoi_multi_workspace_bytes(const int32_t* N_d, int64_t D, int32_t kmin, int32_t kmax,
+                                  const thoi_eval_opts* opts)
+{
+    int64_t total = 0;
+    if (check_multi(N_d, nullptr, D, kmin, kmax, opts, &total) != THOI_OK && !(opts && opts->bias_correct)) return 0;
+    return multi_ws_bytes(N_d, D, kmin, kmax, opts);
+}
+
 thoi_status thoi_reduce_init(const thoi_reduce* red, int64_t D, int32_t kmax, void* stream)
 {
     if (!red || D < 0 || kmax < 0 || kmax > THOI_MAX_K) return THOI_EINVAL;

@@ -13,214 +13,11 @@
 // FP32_REFINE: the FP32 lane engine flags n-plets whose max VIF exceeds tau (or that failed);
 // a follow-up FP64 kernel re-evaluates exactly those and overwrites their results.
 // Results go either to the output planes or to the streaming reducer (reduce_common.hpp).
-#include "nplets_common.hpp"
-#include "reduce_common.hpp"
+#include "nplets_fwd_common.hpp"
 
 namespace thoi {
 
 namespace {
-
-constexpr int kTile = 256;          // n-plets (= threads) per lane-engine tile
-constexpr int kMaxPieces = 24;      // orders per launch class
-constexpr int kWaveTileOut = 8;     // n-plets per wave-engine workgroup (output mode)
-constexpr int kWaveTileRed = 64;    // n-plets per wave-engine workgroup (reduce mode)
-constexpr int kListOrders = THOI_MAX_K + 2;   // k = 0..64 and one "invalid" bucket
-
-// Kernel classes: [lo, hi] of orders evaluated by one launch of the lane engine.
-struct KClass { int lo, hi; };
-constexpr KClass kF32Classes[] = {{0, 8}, {9, 12}, {13, 16}, {17, 20}, {21, 24}};
-constexpr KClass kF64Classes[] = {{0, 6}, {7, 10}, {11, 14}, {15, 18}};
-constexpr int kF32LaneMax = 24;
-constexpr int kF64LaneMax = 18;
-
-struct Piece {
-    int32_t k;
-    int32_t pad;
-    int64_t first;   // RANGE: first lexicographic rank inside C(N, k)
-    int64_t pos0;    // RANGE: output position of `first`
-    int64_t cnt;     // n-plets in the piece
-    int64_t blk0;    // first workgroup of the piece inside its launch
-};
-struct PieceTable {
-    int32_t n;
-    int32_t pad;
-    Piece p[kMaxPieces];
-};
-
-// Bias offsets of Eq. (bias_corrector) are rebuilt on the device from two digamma seeds:
-// psi_j = psi((T-j)/2), psi_j = psi_{j-2} - 2/(T-j).
-struct BiasParams {
-    int32_t on, T;
-    double psi1, psi2;
-};
-
-__device__ __forceinline__ void bias_for(const BiasParams& bp, int k, double& dtc, double& ddtc, double& eta)
-{
-    dtc = ddtc = eta = 0.0;
-    if (!bp.on || k <= 0) return;
-    double pm2 = bp.psi1, pm1 = bp.psi2;   // psi_{j-2}, psi_{j-1} as j advances
-    double P = 0.0, Pkm1 = 0.0, psik = bp.psi1;
-    for (int j = 1; j <= k; ++j) {
-        double pj;
-        if (j == 1) pj = bp.psi1;
-        else if (j == 2) pj = bp.psi2;
-        else { pj = pm2 - 2.0 / (double)(bp.T - j); pm2 = pm1; pm1 = pj; }
-        if (j == k) { Pkm1 = P; psik = pj; }
-        P += pj;
-    }
-    dtc = 0.5 * (P - k * bp.psi1);
-    ddtc = 0.5 * ((k - 1) * psik - Pkm1);
-    eta = 0.5 * (k * log(2.0 / (double)(bp.T - 1)) + P);
-}
-
-struct EvalArgs {
-    const double* Sigma;
-    int32_t N, D;
-    int64_t B;               // output positions per dataset
-    int64_t g_begin;         // RANGE: global index of position 0
-    void* out;
-    int32_t out_f32, write_H;
-    uint8_t* flags;
-    int32_t precision;
-    float vif_tau;
-    WsHeader* hdr;
-    int64_t* refine_list;
-    uint32_t refine_cap;
-    int32_t seg_tiles;       // lane engine: tiles of kTile n-plets per workgroup
-    int32_t wave_tile;       // wave engine: n-plets per workgroup
-    BiasParams bias;
-    // LIST / MASK
-    const int32_t* idx;
-    int32_t kmax_list;
-    const uint64_t* mask;
-    const int64_t* perm;     // [B] positions sorted by order
-    const int64_t* lcnt;     // [kListOrders] per-order counts
-    const int64_t* lbase;    // [kListOrders] first slot in perm
-    const int64_t* lblk0;    // [kListOrders] first workgroup of the order inside its launch
-};
-
-// ------------------------------------------------------------------------------------------------
-// Result handling shared by the engines.  Returns whether the value may enter the reducer.
-// ------------------------------------------------------------------------------------------------
-template <typename F>
-__device__ __forceinline__ bool store_result(const EvalArgs& a, bool reduce, int d, int64_t pos, int k,
-                                             const FactorOut<F>& f, double sumlogd, double dtc, double ddtc,
-                                             double eta, bool fp64_pass, double& omega)
-{
-    const int64_t o = (int64_t)d * a.B + pos;
-    uint8_t flag = 0;
-    F TC, DTC;
-    const bool finite = isfinite(f.ld) && isfinite(f.sa);
-    bool bad = !f.ok || !finite;
-    bool queued = false;
-    if (!fp64_pass && a.precision == THOI_FP32_REFINE) {
-        const bool need = bad || !(f.vmax <= (F)a.vif_tau);
-        // wave-aggregated append to the refine queue
-        const uint64_t ballot = __ballot(need);
-        if (ballot) {
-            const int lane = threadIdx.x & 63;
-            const int leader = __ffsll((unsigned long long)ballot) - 1;
-            uint32_t base = 0;
-            if (lane == leader) base = atomicAdd(&a.hdr->refine_count, (uint32_t)__popcll(ballot));
-            base = __shfl(base, leader, 64);
-            if (need) {
-                const uint32_t slot = base + (uint32_t)__popcll(ballot & __lanemask_lt());
-                if (slot < a.refine_cap) a.refine_list[slot] = o;
-                else raise_status(a.hdr, THOI_EWORKSPACE);
-                flag = THOI_NPLET_REFINED;
-                queued = true;
-            }
-        }
-        bad = false;  // the FP32 values stay until the FP64 pass overwrites them
-    }
-    if (bad) {
-        TC = DTC = (F)__builtin_nan("");
-        flag |= THOI_NPLET_NOT_PD;
-    } else {
-        TC = F(-0.5) * f.ld + (F)dtc;
-        DTC = F(0.5) * (f.ld + f.sa) + (F)ddtc;
-    }
-    const F OM = TC - DTC, SI = TC + DTC;
-    omega = (double)OM;
-    if (!reduce) {
-        const int64_t plane = (int64_t)a.D * a.B;
-        if (a.out_f32) {
-            float* op = static_cast<float*>(a.out);
-            op[o] = (float)TC; op[plane + o] = (float)DTC; op[2 * plane + o] = (float)OM; op[3 * plane + o] = (float)SI;
-            if (a.write_H) op[4 * plane + o] = bad ? __builtin_nanf("") : (float)(0.5 * (k * kLog2PiE + (double)f.ld + sumlogd) - eta);
-        } else {
-            double* op = static_cast<double*>(a.out);
-            op[o] = (double)TC; op[plane + o] = (double)DTC; op[2 * plane + o] = (double)OM; op[3 * plane + o] = (double)SI;
-            if (a.write_H) op[4 * plane + o] = bad ? __builtin_nan("") : 0.5 * (k * kLog2PiE + (double)f.ld + sumlogd) - eta;
-        }
-    }
-    if (a.flags) a.flags[o] = flag;
-    return !bad && !queued;
-}
-
-// ------------------------------------------------------------------------------------------------
-// Lane engine
-// ------------------------------------------------------------------------------------------------
-struct LaneCtx {
-    int d;
-    int64_t local;       // index of the n-plet inside its piece
-    int64_t first, pos0;
-    int N;
-    int kb;
-    bool reduce;
-    double dtc, ddtc, eta;
-};
-
-template <typename F, int K, int MODE>
-__device__ __forceinline__ bool lane_task(const EvalArgs& a, const LaneCtx& cx, const F* sR, const double* sLogd,
-                                          const uint64_t* sBin, double& omega, int64_t& gidx)
-{
-    int c[K > 0 ? K : 1];
-    int64_t pos;
-    if constexpr (MODE == THOI_SEL_RANGE) {
-        unrank_lex<K>((uint64_t)(cx.first + cx.local), cx.N, sBin, cx.kb, c);
-        pos = cx.pos0 + cx.local;
-        gidx = a.g_begin + pos;
-    } else if constexpr (MODE == THOI_SEL_LIST) {
-        pos = a.perm[cx.first + cx.local];
-        gidx = pos;
-        const int32_t* row = a.idx + pos * a.kmax_list;
-#pragma unroll
-        for (int i = 0; i < K; ++i) c[i] = row[i];
-    } else {
-        pos = a.perm[cx.first + cx.local];
-        gidx = pos;
-        uint64_t m = a.mask[pos];
-#pragma unroll
-        for (int i = 0; i < K; ++i) { c[i] = __builtin_ctzll(m); m &= m - 1; }
-    }
-    const FactorOut<F> f = lane_factor<F, K>(c, sR, cx.N);
-    double sumlogd = 0.0;
-    if (a.write_H) {
-#pragma unroll
-        for (int i = 0; i < K; ++i) sumlogd += sLogd[c[i]];
-    }
-    return store_result<F>(a, cx.reduce, cx.d, pos, K, f, sumlogd, cx.dtc, cx.ddtc, cx.eta, false, omega);
-}
-
-template <typename F, int K, int KHI, int MODE>
-__device__ __forceinline__ bool dispatch_k(int k, const EvalArgs& a, const LaneCtx& cx, const F* sR,
-                                           const double* sLogd, const uint64_t* sBin, double& omega, int64_t& gidx)
-{
-    if (k == K) return lane_task<F, K, MODE>(a, cx, sR, sLogd, sBin, omega, gidx);
-    if constexpr (K < KHI) return dispatch_k<F, K + 1, KHI, MODE>(k, a, cx, sR, sLogd, sBin, omega, gidx);
-    return false;
-}
-
-// LDS: sR [N*N] F | sIsd [N] f64 | sLogd [N] f64 | sBin [N*kb] u64 | (reduce) RedLds
-__host__ __device__ inline size_t lane_stage_bytes(int N, int kb, int fsize)
-{
-    size_t off = (size_t)N * N * fsize;
-    off = (off + 15) / 16 * 16;
-    off += (size_t)N * 8 * 2;
-    off += (size_t)N * kb * 8;
-    return (off + 15) / 16 * 16;
-}
 
 template <typename F, int KLO, int KHI, int MODE, bool RED>
 __global__ __launch_bounds__(kTile) void k_eval_lane(EvalArgs a, PieceTable tab, RedArgs red)
@@ -286,21 +83,6 @@ __global__ __launch_bounds__(kTile) void k_eval_lane(EvalArgs a, PieceTable tab,
         if constexpr (RED) red_push(S, red, k, valid, omega, gidx);
     }
     if constexpr (RED) red_end(S, red, a.hdr, d, k);
-}
-
-// ------------------------------------------------------------------------------------------------
-// Wave engine kernel: orders above the register classes (one wavefront per n-plet, FP64).
-// grid (workgroups, D), block 64.
-// LDS: sR [N*N] f64 | sIsd [N] | sLogd [N] | sBin [N*64] (RANGE) | sM [64*ks] | sInv [64] |
-//      cidx [64] int | res_v [64] | res_g [64] | res_ok [64] | (reduce) RedLds
-// ------------------------------------------------------------------------------------------------
-__host__ __device__ inline size_t wave_stage_bytes(int N, int kmax, bool with_bin)
-{
-    const int ks = kmax + 1;
-    size_t off = (size_t)N * N * 8 + (size_t)N * 16 + (with_bin ? (size_t)N * 64 * 8 : 0);
-    off += (size_t)64 * ks * 8 + 64 * 8 + 64 * 4;
-    off += 64 * 8 + 64 * 8 + 64 * 4;
-    return (off + 15) / 16 * 16;
 }
 
 template <int MODE, bool RED>
@@ -474,80 +256,6 @@ __global__ __launch_bounds__(64) void k_refine(EvalArgs a, RangeOrders ro, RedAr
     }
 }
 
-// ------------------------------------------------------------------------------------------------
-// Final merge of the streaming reduction: one workgroup per (order k, dataset d).
-// ------------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_red_final(RedArgs red, WsHeader* hdr)
-{
-    __shared__ RedLds S;
-    const int k = blockIdx.x, d = blockIdx.y;
-    const int K = red.topk;
-    if (K <= 0) return;
-    double* tv = red.top_val + ((int64_t)d * (red.kmax + 1) + k) * 2 * K;
-    int64_t* tg = red.top_g + ((int64_t)d * (red.kmax + 1) + k) * 2 * K;
-    for (int i = threadIdx.x; i < 2 * K; i += blockDim.x) {
-        const int l = i / K, j = i % K;
-        const bool has = tg[i] >= 0;
-        S.key[l][0][j] = has ? red_list_key(l, tv[i]) : kKeyEmpty;
-        S.g[l][0][j] = has ? tg[i] : kGEmpty;
-    }
-    if (threadIdx.x == 0) { S.cur[0] = S.cur[1] = 0; }
-    __syncthreads();
-    const uint32_t nseg = min(hdr->seg_next, red.seg_cap);
-    for (uint32_t s = 0; s < nseg; ++s) {
-        const SegHdr h = red.seg_hdr[s];
-        if (h.d != d || h.k != k) continue;          // uniform
-        for (int l = 0; l < 2; ++l) {
-            const uint64_t* bk = red.seg_key + ((int64_t)s * 2 + l) * K;
-            const int64_t* bg = red.seg_g + ((int64_t)s * 2 + l) * K;
-            const int c = S.cur[l];
-            if (!red_less(bk[0], bg[0], S.key[l][c][K - 1], S.g[l][c][K - 1])) continue;   // uniform
-            red_merge_sorted(S, l, K, bk, bg, K);
-        }
-    }
-    const uint32_t nlate = min(hdr->late_next, red.late_cap);
-    for (uint32_t b0 = 0; b0 < nlate; b0 += blockDim.x) {
-        const uint32_t i = b0 + threadIdx.x;
-        bool mine = false;
-        double v = 0.0;
-        int64_t g = 0;
-        if (i < nlate) {
-            const LateEntry e = red.late[i];
-            mine = e.d == d && e.k == k;
-            v = e.v;
-            g = e.g;
-        }
-        red_offer(S, 0, K, mine, red_list_key(0, v), g);
-        red_offer(S, 1, K, mine, red_list_key(1, v), g);
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < 2 * K; i += blockDim.x) {
-        const int l = i / K, j = i % K;
-        const uint64_t key = S.key[l][S.cur[l]][j];
-        const bool has = key != kKeyEmpty;
-        tv[i] = has ? red_list_val(l, key) : __builtin_nan("");
-        tg[i] = has ? S.g[l][S.cur[l]][j] : -1;
-    }
-}
-
-__global__ void k_red_init(double* top_val, int64_t* top_g, int64_t ntop, unsigned long long* hist, int64_t nhist)
-{
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ntop; i += stride) {
-        top_val[i] = __builtin_nan("");
-        top_g[i] = -1;
-    }
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nhist; i += stride) hist[i] = 0;
-}
-
-// ------------------------------------------------------------------------------------------------
-// LIST / MASK: order bucketing on the device.
-// ------------------------------------------------------------------------------------------------
-__global__ void k_ws_clear(uint32_t* p, int64_t n)
-{
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0;
-}
-
 // grid ceil(B/256): order of every row (THOI_MAX_K + 1 = invalid) and per-order counts.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_list_classify(EvalArgs a, int reduce, int64_t Bn, uint8_t* __restrict__ korder,
@@ -658,35 +366,6 @@ __global__ __launch_bounds__(256) void k_list_scatter(int64_t Bn, const uint8_t*
 // ------------------------------------------------------------------------------------------------
 // Host side
 // ------------------------------------------------------------------------------------------------
-int64_t sel_B(const thoi_nplets* sel) { return sel->mode == THOI_SEL_RANGE ? sel->g_count : sel->B; }
-
-int sel_kmax(const thoi_nplets* sel, int N)
-{
-    if (sel->mode == THOI_SEL_RANGE) return sel->kmax;
-    if (sel->mode == THOI_SEL_LIST) return sel->kmax_list < THOI_MAX_K ? sel->kmax_list : THOI_MAX_K;
-    return N < THOI_MAX_K ? N : THOI_MAX_K;
-}
-
-template <typename F>
-const KClass* classes_for(int& n)
-{
-    if constexpr (sizeof(F) == 4) { n = (int)(sizeof(kF32Classes) / sizeof(KClass)); return kF32Classes; }
-    n = (int)(sizeof(kF64Classes) / sizeof(KClass));
-    return kF64Classes;
-}
-
-int lane_max_for(int precision) { return precision == THOI_FP64 ? kF64LaneMax : kF32LaneMax; }
-
-template <typename F>
-int class_of(int k)
-{
-    int n = 0;
-    const KClass* cls = classes_for<F>(n);
-    int c = 0;
-    while (c < n - 1 && k > cls[c].hi) ++c;
-    return c;
-}
-
 // Launch plan of a call: workgroups per class and per wave launch; exact for RANGE, an upper
 // bound for LIST / MASK.
 struct Plan {
@@ -836,7 +515,6 @@ WaveKernel wave_kernel(bool reduce)
     return reduce ? k_eval_wave<MODE, true> : k_eval_wave<MODE, false>;
 }
 
-size_t red_lds(bool reduce) { return reduce ? sizeof(RedLds) : 0; }
 
 template <typename F, int MODE>
 void launch_engines(EvalArgs& a, const Plan& P, const RedArgs& red, hipStream_t s)

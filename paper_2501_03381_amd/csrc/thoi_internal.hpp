@@ -58,5 +58,11 @@ thoi_status launch_backward(const double* Sigma, int64_t D, int32_t N, const tho
 size_t backward_ws_bytes(int64_t D, int32_t N, const thoi_nplets* sel, const thoi_eval_opts* opts);
 size_t backward_lds_bytes(int32_t N, const thoi_nplets* sel);
 thoi_status launch_reduce_init(const thoi_reduce* red, int64_t D, int32_t kmax, hipStream_t s);
+thoi_status launch_multi(const double* Sigma, const int32_t* N_d, const int32_t* T_d, int64_t D, int32_t kmin,
+                         int32_t kmax, const thoi_eval_opts* opts, void* out, uint8_t* flags, void* ws,
+                         size_t ws_bytes, hipStream_t s);
+size_t multi_ws_bytes(const int32_t* N_d, int64_t D, int32_t kmin, int32_t kmax, const thoi_eval_opts* opts);
+size_t multi_lds_bytes(int32_t nmax, int32_t kmax, const thoi_eval_opts* opts);
+int multi_lane_max(int32_t precision);
 
 }  // namespace thoi
