@@ -158,6 +158,8 @@ thoi_status check_eval(const double* Sigma, int64_t D, int32_t N, const thoi_npl
         if (opts->T < kmax + 2 || opts->T < 3) return THOI_EINVAL;
     }
     if (opts->write_entropy != 0 && opts->write_entropy != 1) return THOI_EINVAL;
+    if (opts->seg_tiles < 0 || opts->grid_blocks < 0) return THOI_EINVAL;
+    if (opts->seg_tiles > 4096) return THOI_EUNSUPPORTED;
     if (forward) {
         if (opts->reduce) {
             const thoi_reduce* r = opts->reduce;

@@ -380,7 +380,7 @@ struct Plan {
 };
 
 template <typename F>
-Plan make_plan(int N, const thoi_nplets* sel, bool reduce, int precision)
+Plan make_plan(int N, const thoi_nplets* sel, bool reduce, int precision, int seg_tiles_hint)
 {
     Plan P{};
     const KClass* cls = classes_for<F>(P.ncls);
@@ -395,6 +395,7 @@ Plan make_plan(int N, const thoi_nplets* sel, bool reduce, int precision)
         P.seg_tiles = (int)((tiles + 16383) / 16384);
         if (P.seg_tiles < 1) P.seg_tiles = 1;
     }
+    if (seg_tiles_hint > 0) P.seg_tiles = seg_tiles_hint;
     const int64_t per_blk = (int64_t)kTile * P.seg_tiles;
     if (sel->mode == THOI_SEL_RANGE) {
         int64_t g = 0;
@@ -464,8 +465,8 @@ EvalWs eval_layout(int64_t D, int32_t N, const thoi_nplets* sel, const thoi_eval
     }
     if (reduce && opts->reduce->topk > 0) {
         const int K = opts->reduce->topk;
-        const Plan P = opts->precision == THOI_FP64 ? make_plan<double>(N, sel, true, opts->precision)
-                                                    : make_plan<float>(N, sel, true, opts->precision);
+        const Plan P = opts->precision == THOI_FP64 ? make_plan<double>(N, sel, true, opts->precision, opts->seg_tiles)
+                                                    : make_plan<float>(N, sel, true, opts->precision, opts->seg_tiles);
         const int64_t segs = P.seg_cap * D;
         w.seg_cap = (uint32_t)(segs > 0 ? segs : 1);
         w.seg_key_off = off; off = align_up(off + (size_t)w.seg_cap * 2 * K * 8, 256);
@@ -663,12 +664,12 @@ thoi_status launch_eval(const double* Sigma, int64_t D, int32_t N, const thoi_np
     if (D == 0 || a.B == 0) return hip_status(hipGetLastError());
 
     if (opts->precision == THOI_FP64) {
-        const Plan P = make_plan<double>(N, sel, reduce, opts->precision);
+        const Plan P = make_plan<double>(N, sel, reduce, opts->precision, opts->seg_tiles);
         a.seg_tiles = P.seg_tiles;
         a.wave_tile = P.wave_tile;
         launch_forward<double>(a, sel, P, red, w, base, s);
     } else {
-        const Plan P = make_plan<float>(N, sel, reduce, opts->precision);
+        const Plan P = make_plan<float>(N, sel, reduce, opts->precision, opts->seg_tiles);
         a.seg_tiles = P.seg_tiles;
         a.wave_tile = P.wave_tile;
         launch_forward<float>(a, sel, P, red, w, base, s);

@@ -102,3 +102,35 @@ def test_multi_refinement_and_reduce(env):
             assert np.allclose(tv[d, k, 1, :len(bot)], [x[0] for x in bot], atol=1e-6)
             assert np.allclose(om[tg[d, k, 0, :len(top)]], tv[d, k, 0, :len(top)], atol=1e-6)
             assert h[d, k].sum() == (ords == k).sum()
+
+
+def test_tuning_knobs_do_not_change_results(env, tmp_path, monkeypatch):
+    torch, api, B, synth, orc = env
+    from paper_2501_03381_amd import tune
+    monkeypatch.setenv("THOI_TUNE_CACHE", str(tmp_path / "tune.json"))
+    Sd = api.gc_covariance(dev(torch, synth.latent_20(T=2000)))
+    say("seg_tiles 1 / 3 / 8 give identical RANGE results")
+    sel = api.range_selection(20, 3, 20)
+    outs = []
+    for st in (1, 3, 8):
+        ev = api.Evaluator(1, 20, sel, api.make_opts("fp32_refine", seg_tiles=st), Sd.device)
+        o, f = ev(Sd)
+        outs.append((o.clone(), f.clone()))
+    for o, f in outs[1:]:
+        assert torch.equal(o, outs[0][0]) and torch.equal(f, outs[0][1])
+    say("tune_range")
+    r = tune.tune_range(Sd, 3, 20, candidates=(1, 2))
+    assert r["seg_tiles"] in (1, 2) and r["ms"] > 0
+    Xs = uneven(synth, 20, 8, 20, 500, 1000, 16)
+    Sig = [dev(torch, orc.gc_covariance(X)) for X in Xs]
+    flat, Ns = api.pack_covariances(Sig)
+    say("multi grid/segment knobs give identical results")
+    res = []
+    for st, gb in ((1, 0), (4, 64), (2, 7)):
+        ev = api.MultiEvaluator(Ns, 3, 6, flat.device, "fp32_refine", seg_tiles=st, grid_blocks=gb)
+        o, f = ev(flat)
+        res.append(o.clone())
+    assert all(torch.equal(res[0], r_) for r_ in res[1:])
+    say("tune_multi")
+    t = tune.tune_multi(flat, Ns, 3, 6, seg_candidates=(1, 4), grid_candidates=(0, 256))
+    assert t["seg_tiles"] in (1, 4) and t["grid_blocks"] in (0, 256)
