@@ -42,6 +42,10 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the CPU oracle sample")
     p.add_argument("--skip-fp64", action="store_true")
+    p.add_argument("--workload", default="latent20",
+                   choices=["latent20", "ar1_30", "uneven1024", "latent100_grad"],
+                   help="latent20: the headline N=20 step (default); the others time the remaining "
+                        "configurations of the method (one JSON line each)")
     p.add_argument("--profile-kernels", action="store_true",
                    help="only run a 256 MiB device copy and the dominant evaluation launch 3 times each "
                         "(for hardware-counter runs), then exit")
@@ -140,6 +144,78 @@ def kernel_ms(torch, fn, reps=50):
     return best
 
 
+def bench_ar1_30(torch, np, api, B, synth, dev, args):
+    """N=30, T=1200 AR(1) mixture: all 1,073,741,358 n-plets of orders 3..30 with a streaming
+    per-order top-100 / bottom-100 Omega and a 256-bin Omega histogram (no per-n-plet output).
+    Histogram ranges come from a pilot pass over a seeded sample of each order, widened by 25%."""
+    N, kmin, kmax = 30, 3, 30
+    X = torch.from_numpy(synth.ar1_30()[None]).to(dev)
+    Sigma = api.gc_covariance(X)
+    total = B.thoi_count(N, kmin, kmax)
+    rng = np.random.default_rng(2)
+    lohi = np.zeros((kmax + 1, 2))
+    lohi[:, 0], lohi[:, 1] = -1.0, 1.0
+    for k in range(kmin, kmax + 1):
+        nk = math.comb(N, k)
+        ranks = np.unique(rng.integers(0, nk, min(nk, 20000)))
+        off = B.thoi_count(N, kmin, k - 1) if k > kmin else 0
+        rows = np.array([list(B.thoi_unrank_host(N, kmin, int(off + r))) for r in ranks], dtype=np.int32)
+        o, _ = api.nplets_measures(Sigma, nplets=torch.from_numpy(rows).to(dev), precision="fp64",
+                                   out_dtype=torch.float64)
+        v = o[2].cpu().numpy()
+        lo, hi = float(v.min()), float(v.max())
+        pad = 0.25 * max(hi - lo, 1e-6)
+        lohi[k] = (lo - pad, hi + pad)
+    res = {}
+    for prec in ("fp32_refine", "fp64"):
+        st = api.ReduceState(1, kmax, 100, 256, lohi, dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        api.nplets_reduce(Sigma, orders=(kmin, kmax), topk=100, hist_bins=256, hist_range=lohi, precision=prec,
+                          state=st, check=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tv, tg, h = st.result()
+        res[prec] = {"seconds": dt, "nplets_per_s": total / dt, "hist_total": int(h.sum()),
+                     "max_omega": float(np.nanmax(tv[0, :, 0, 0])), "min_omega": float(np.nanmin(tv[0, :, 1, 0]))}
+    return {"workload": "ar1_30: N=30, T=1200, seed 2, all orders 3..30 (1,073,741,358 n-plets), streaming "
+                        "top-100/bottom-100 + 256-bin histogram per order", "metric": "n-plets/s",
+            "value": res["fp32_refine"]["nplets_per_s"], "unit": "n-plets/s", "nplets": total, "detail": res}
+
+
+def bench_uneven(torch, np, api, B, synth, dev, args):
+    """1024 datasets with N ~ U{10..40}, T ~ U{500..5000} (k-factor models): all n-plets of orders
+    3..5 of every dataset in one multi-dataset call (persistent launch per class), FP32 + refine,
+    launch knobs from the autotuner.  Copula and covariance run per dataset beforehand."""
+    from paper_2501_03381_amd import tune
+    Xs = synth.uneven_many(D=1024, seed=3)
+    Sig = [api.gc_covariance(torch.from_numpy(X).to(dev)) for X in Xs]
+    flat, Ns = api.pack_covariances(Sig)
+    t = tune.tune_multi(flat, Ns, 3, 5, use_cache=False)
+    ev = api.MultiEvaluator(Ns, 3, 5, dev, "fp32_refine", seg_tiles=t["seg_tiles"], grid_blocks=t["grid_blocks"])
+    ms = kernel_ms(torch, lambda st: ev(flat, stream=st.value), reps=10)
+    return {"workload": "uneven1024: 1024 datasets, N~U{10..40}, T~U{500..5000}, seed 3, orders 3..5",
+            "metric": "n-plets/s", "value": ev.total / (ms * 1e-3), "unit": "n-plets/s", "nplets": ev.total,
+            "ms_per_call": ms, "tuned": {"seg_tiles": t["seg_tiles"], "grid_blocks": t["grid_blocks"]},
+            "status": ev.status()}
+
+
+def bench_grad(torch, np, api, B, synth, dev, args):
+    """N=100, T=2000 latent model: 10^5 n-plets of order U{8..20}; forward (Omega, S, TC, DTC) plus
+    the adjoint d(sum Omega)/d Sigma."""
+    X, idx = synth.latent_100()
+    Sigma = api.gc_covariance(torch.from_numpy(X).to(dev))
+    I = torch.from_numpy(idx).to(dev)
+    g = torch.zeros((4, 1, idx.shape[0]), dtype=torch.float32, device=dev)
+    g[2] = 1.0
+    fwd = kernel_ms(torch, lambda st: api.nplets_measures(Sigma, nplets=I, precision="fp32_refine", check=False),
+                    reps=5)
+    bwd = kernel_ms(torch, lambda st: api.measures_backward(Sigma, g, nplets=I), reps=5)
+    return {"workload": "latent100_grad: N=100, T=2000, seed 4, 1e5 n-plets of order 8..20", "metric": "n-plets/s",
+            "value": idx.shape[0] / (fwd * 1e-3), "unit": "n-plets/s", "forward_ms": fwd, "backward_ms": bwd,
+            "backward_nplets_per_s": idx.shape[0] / (bwd * 1e-3)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -159,6 +235,11 @@ def main():
     X = torch.from_numpy(synth.latent_20()[None]).to(dev)
     total = B.thoi_count(N, kmin, kmax)
     use_graph = not args.no_graph
+
+    if args.workload != "latent20":
+        extra = {"ar1_30": bench_ar1_30, "uneven1024": bench_uneven, "latent100_grad": bench_grad}[args.workload]
+        print(json.dumps(extra(torch, np, api, B, synth, dev, args)), flush=True)
+        return
 
     if args.profile_kernels:
         # calibration: a plain copy of known size, then the dominant evaluation launch
