@@ -43,7 +43,7 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the CPU oracle sample")
     p.add_argument("--skip-fp64", action="store_true")
     p.add_argument("--workload", default="latent20",
-                   choices=["latent20", "ar1_30", "uneven1024", "latent100_grad"],
+                   choices=["latent20", "ar1_30", "uneven1024", "latent100_grad", "classes"],
                    help="latent20: the headline N=20 step (default); the others time the remaining "
                         "configurations of the method (one JSON line each)")
     p.add_argument("--profile-kernels", action="store_true",
@@ -216,6 +216,27 @@ def bench_grad(torch, np, api, B, synth, dev, args):
             "backward_nplets_per_s": idx.shape[0] / (bwd * 1e-3)}
 
 
+def bench_classes(torch, np, api, B, synth, dev, args):
+    """Per-order timing of the N=20 evaluation (each order alone, FP32 and FP64): where the step's
+    time goes and the achieved FLOP rate of each order."""
+    N = 20
+    X = torch.from_numpy(synth.latent_20()[None]).to(dev)
+    Sigma = api.gc_covariance(X)
+    rows = []
+    for prec in ("fp32", "fp64"):
+        odt = torch.float32 if prec == "fp32" else torch.float64
+        nil = api.Evaluator(1, N, api.range_selection(N, 3, 3, 0, 0), api.make_opts(prec, odt), dev, odt)
+        t_nil = kernel_ms(torch, lambda st: nil(Sigma, stream=st.value), reps=50)
+        for k in range(3, N + 1):
+            ev = api.Evaluator(1, N, api.range_selection(N, k, k), api.make_opts(prec, odt), dev, odt)
+            t = kernel_ms(torch, lambda st: ev(Sigma, stream=st.value), reps=20) - t_nil
+            n = math.comb(N, k)
+            rows.append({"precision": prec, "k": k, "nplets": n, "us": round(t * 1e3, 2),
+                         "tflops": round(n * flops(k) / max(t, 1e-9) / 1e9, 2),
+                         "gnplets_s": round(n / max(t, 1e-9) / 1e6, 2)})
+    return {"workload": "per-order timing, latent_20", "empty_call_us": round(t_nil * 1e3, 2), "rows": rows}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -237,7 +258,8 @@ def main():
     use_graph = not args.no_graph
 
     if args.workload != "latent20":
-        extra = {"ar1_30": bench_ar1_30, "uneven1024": bench_uneven, "latent100_grad": bench_grad}[args.workload]
+        extra = {"ar1_30": bench_ar1_30, "uneven1024": bench_uneven, "latent100_grad": bench_grad,
+                 "classes": bench_classes}[args.workload]
         print(json.dumps(extra(torch, np, api, B, synth, dev, args)), flush=True)
         return
 
