@@ -381,3 +381,23 @@ def test_deterministic(env):
     a, fa = api.nplets_measures(Sd, orders=(3, 20), precision="fp32_refine")
     b, fb = api.nplets_measures(Sd, orders=(3, 20), precision="fp32_refine")
     assert torch.equal(a, b) and torch.equal(fa, fb)
+
+
+def test_range_unranking_wide_systems(env):
+    """RANGE unranking with 64-bit binomials (N > 34) and windows deep inside an order."""
+    torch, api, B, synth, orc = env
+    rng = np.random.default_rng(21)
+    for N, kmin, kmax, window in ((40, 3, 4, None), (62, 1, 2, None), (50, 5, 6, (2_100_000, 40_000)),
+                                  (60, 29, 30, (10 ** 17, 3000))):
+        S = synth.random_spd(rng, N, 30.0)
+        total = B.thoi_count(N, kmin, kmax)
+        g0, cnt = (0, total) if window is None else window
+        say(f"RANGE fp64 N={N} orders {kmin}..{kmax} window {g0}+{cnt}")
+        out, _ = api.nplets_measures(dev(torch, S), orders=(kmin, kmax), g_range=(g0, cnt), precision="fp64",
+                                     out_dtype=torch.float64)
+        out = host(out)
+        pick = np.unique(np.concatenate([rng.integers(0, cnt, 400), [0, cnt - 1]]))
+        rows = orc.pad_list([B.thoi_unrank_host(N, kmin, int(g0 + p)) for p in pick], kmax=kmax)
+        ref, _, _ = orc.eval_list(S, rows)
+        for m in range(4):
+            assert_close(out[m, pick], ref[m], 1e-8, f"N={N} m={m}")
