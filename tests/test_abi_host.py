@@ -134,3 +134,51 @@ def test_workspace_sizes(B):
     assert B.thoi_workspace_bytes(B.THOI_WS_COPULIZE, 1, 1000, 10) == 256          # one chunk: no scratch
     assert B.thoi_workspace_bytes(B.THOI_WS_COPULIZE, 1, 10000, 20) > 10000 * 20 * 12
     assert B.thoi_ws_status_offset() == 0
+
+
+def test_struct_layouts_match_header(B, tmp_path):
+    """ctypes mirrors of the header's structs have the C sizes and field offsets (gcc, offsetof)."""
+    import subprocess
+    fields = {
+        "thoi_nplets": ["mode", "kmin", "kmax", "g_begin", "g_count", "idx", "kmax_list", "mask", "B"],
+        "thoi_reduce": ["topk", "hist_bins", "hist_lo_hi", "top_val", "top_g", "hist"],
+        "thoi_eval_opts": ["precision", "out_dtype", "vif_tau", "bias_correct", "T", "write_entropy", "reduce",
+                           "seg_tiles", "grid_blocks"],
+    }
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "thoi.h"', "int main(void) {"]
+    for st, fs in fields.items():
+        src.append(f'printf("{st} %zu\\n", sizeof({st}));')
+        for f in fs:
+            src.append(f'printf("{st}.{f} %zu\\n", offsetof({st}, {f}));')
+    src.append("return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)], text=True).splitlines())
+    mirror = {"thoi_nplets": B.ThoiNplets, "thoi_reduce": B.ThoiReduce, "thoi_eval_opts": B.ThoiEvalOpts}
+    for st, cls in mirror.items():
+        assert int(got[st]) == ctypes.sizeof(cls), st
+        for f in fields[st]:
+            assert int(got[f"{st}.{f}"]) == getattr(cls, f).offset, (st, f)
+
+
+def test_multi_offsets_and_argument_errors(B):
+    N_d = np.array([5, 12, 3, 30, 1], dtype=np.int32)
+    off = B.thoi_multi_offsets(N_d, 3, 5)
+    ref = np.concatenate([[0], np.cumsum([sum(math.comb(int(n), k) for k in range(3, 6) if k <= n) for n in N_d])])
+    assert np.array_equal(off, ref)
+    L = B.lib()
+    fake = ctypes.c_void_p(0x1000)
+    Np = N_d.ctypes.data_as(ctypes.c_void_p)
+    opts = B.ThoiEvalOpts(precision=B.THOI_FP32_REFINE, out_dtype=B.THOI_DTYPE_F32)
+    call = lambda N, D, kmin, kmax, o, T=None, out=fake: L.thoi_nplets_eval_multi(fake, N, T, D, kmin, kmax,
+                                                                                   ctypes.byref(o), out, None, fake,
+                                                                                   1 << 30, None)
+    assert call(Np, 5, 3, 25, opts) == B.THOI_EUNSUPPORTED      # beyond the register classes
+    assert call(Np, 5, 5, 3, opts) == B.THOI_EINVAL
+    assert call(Np, 5, 3, 5, B.ThoiEvalOpts(precision=0, out_dtype=0, bias_correct=1)) == B.THOI_EINVAL  # no T_d
+    bad = np.array([5, 63], dtype=np.int32)
+    assert call(bad.ctypes.data_as(ctypes.c_void_p), 2, 3, 5, opts) == B.THOI_EUNSUPPORTED
+    assert call(Np, 5, 3, 5, opts, out=None) == B.THOI_EINVAL
+    assert call(Np, 5, 3, 5, B.ThoiEvalOpts(precision=1, out_dtype=1, seg_tiles=-1)) == B.THOI_EINVAL
