@@ -4,16 +4,19 @@
 // index.
 //
 // Design: a column is cut into chunks of kChunk samples.  One workgroup sorts one chunk of
-// (orderable key, sample index) pairs with a bitonic network in LDS (96 KB).  With a single
-// chunk the sorted position is the rank; otherwise the sorted chunks go to the workspace and
-// a second kernel adds, for every element, its lower bound in each of the other chunks.
+// (orderable key, sample index) pairs with a bitonic network in LDS.  With a single chunk the
+// sorted position is the rank.  Otherwise the sorted chunks go to the workspace and a merge
+// workgroup per chunk ranks its elements against every other chunk of the column: the other
+// chunk is staged in LDS and each thread, owning kPerThread consecutive sorted elements, does one
+// binary search and walks forward for the rest (the positions are monotone).
 #include "thoi_internal.hpp"
 
 namespace thoi {
 namespace {
 
-constexpr int kChunk = 8192;          // samples per LDS sort
-constexpr int kSortThreads = 1024;
+constexpr int kChunk = 1024;          // samples per LDS sort
+constexpr int kSortThreads = 256;
+constexpr int kPerThread = kChunk / kSortThreads;
 
 // Monotone map of a double onto uint64 (total order; -0.0 is folded onto +0.0).
 __device__ __forceinline__ uint64_t order_key(double x)
@@ -46,8 +49,8 @@ __device__ __forceinline__ bool pair_less(uint64_t ka, uint32_t ia, uint64_t kb,
 template <typename ZT>
 __global__ __launch_bounds__(kSortThreads) void k_copula_sort(const double* __restrict__ X, int64_t T, int64_t N,
                                                                void* __restrict__ Z, uint64_t* __restrict__ wkey,
-                                                               uint32_t* __restrict__ widx, int32_t* __restrict__ nanflag,
-                                                               WsHeader* hdr)
+                                                               uint32_t* __restrict__ widx,
+                                                               int32_t* __restrict__ nanflag, WsHeader* hdr)
 {
     __shared__ uint64_t skey[kChunk];
     __shared__ uint32_t sidx[kChunk];
@@ -66,7 +69,7 @@ __global__ __launch_bounds__(kSortThreads) void k_copula_sort(const double* __re
     bool has_nan = false;
     for (int i = threadIdx.x; i < P; i += blockDim.x) {
         if (i < n) {
-            double x = Xd[(t0 + i) * N + c];
+            const double x = Xd[(t0 + i) * N + c];
             has_nan |= isnan(x);
             skey[i] = order_key(x);
             sidx[i] = (uint32_t)(t0 + i);
@@ -84,8 +87,8 @@ __global__ __launch_bounds__(kSortThreads) void k_copula_sort(const double* __re
                 const int lo = 2 * i - (i & (stride - 1));
                 const int hi = lo + stride;
                 const bool asc = (lo & size) == 0;
-                uint64_t ka = skey[lo], kb = skey[hi];
-                uint32_t ia = sidx[lo], ib = sidx[hi];
+                const uint64_t ka = skey[lo], kb = skey[hi];
+                const uint32_t ia = sidx[lo], ib = sidx[hi];
                 if (pair_less(kb, ib, ka, ia) == asc) {
                     skey[lo] = kb; skey[hi] = ka;
                     sidx[lo] = ib; sidx[hi] = ia;
@@ -100,7 +103,7 @@ __global__ __launch_bounds__(kSortThreads) void k_copula_sort(const double* __re
         if (bad && threadIdx.x == 0) raise_status(hdr, THOI_EINVAL_DATA);
         for (int p = threadIdx.x; p < n; p += blockDim.x) {
             const int64_t t = sidx[p];
-            double z = bad ? __builtin_nan("") : normal_score(p + 1, T);
+            const double z = bad ? __builtin_nan("") : normal_score(p + 1, T);
             store_z<ZT>(Z, (d * T + t) * N + c, z);
         }
     } else {
@@ -109,51 +112,72 @@ __global__ __launch_bounds__(kSortThreads) void k_copula_sort(const double* __re
             wkey[base + p] = skey[p];
             widx[base + p] = sidx[p];
         }
-        if (threadIdx.x == 0 && snan) {
-            atomicOr(&nanflag[d * N + c], 1);
-            raise_status(hdr, THOI_EINVAL_DATA);
-        }
+        if (threadIdx.x == 0) nanflag[(d * N + c) * nchunks + q] = snan;   // every chunk writes its own flag
     }
 }
 
-// Number of pairs in the sorted run [key, idx][0..n) that are below (k, i).
-__device__ __forceinline__ int64_t lower_bound_pairs(const uint64_t* __restrict__ key, const uint32_t* __restrict__ idx,
-                                                     int n, uint64_t k, uint32_t i)
-{
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (pair_less(key[mid], idx[mid], k, i)) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
-// grid (ceil(kChunk/256), nchunks, N*D), block 256: element p of sorted chunk q.
+// grid (nchunks, N*D), block kSortThreads: ranks of sorted chunk q of column (d, c).
 template <typename ZT>
-__global__ __launch_bounds__(256) void k_copula_merge(int64_t T, int64_t N, int nchunks, void* __restrict__ Z,
-                                                      const uint64_t* __restrict__ wkey,
-                                                      const uint32_t* __restrict__ widx,
-                                                      const int32_t* __restrict__ nanflag)
+__global__ __launch_bounds__(kSortThreads) void k_copula_merge(int64_t T, int64_t N, int nchunks, void* __restrict__ Z,
+                                                               const uint64_t* __restrict__ wkey,
+                                                               const uint32_t* __restrict__ widx,
+                                                               const int32_t* __restrict__ nanflag, WsHeader* hdr)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    const int q = blockIdx.y;
-    const int64_t c = blockIdx.z % N, d = blockIdx.z / N;
-    const int nq = (int)min<int64_t>(kChunk, T - (int64_t)q * kChunk);
-    if (p >= nq) return;
+    __shared__ uint64_t okey[kChunk];
+    __shared__ uint32_t oidx[kChunk];
+    __shared__ int sbad;
+    const int q = blockIdx.x;
+    const int64_t c = blockIdx.y % N, d = blockIdx.y / N;
     const int64_t col = (d * N + c) * nchunks;
-    const uint64_t* key = wkey + (col + q) * (int64_t)kChunk;
-    const uint32_t* idx = widx + (col + q) * (int64_t)kChunk;
-    const uint64_t k = key[p];
-    const uint32_t i = idx[p];
-    int64_t rank = p;
+    const int nq = (int)min<int64_t>(kChunk, T - (int64_t)q * kChunk);
+    if (threadIdx.x == 0) {
+        int bad = 0;
+        for (int o = 0; o < nchunks; ++o) bad |= nanflag[col + o];
+        sbad = bad;
+        if (bad && q == 0) raise_status(hdr, THOI_EINVAL_DATA);
+    }
+    // this thread's elements: sorted positions p0 .. p0 + kPerThread - 1 of chunk q
+    const int p0 = threadIdx.x * kPerThread;
+    uint64_t mk[kPerThread];
+    uint32_t mi[kPerThread];
+    int64_t rank[kPerThread];
+#pragma unroll
+    for (int e = 0; e < kPerThread; ++e) {
+        const int p = p0 + e;
+        mk[e] = p < nq ? wkey[(col + q) * (int64_t)kChunk + p] : ~0ull;
+        mi[e] = p < nq ? widx[(col + q) * (int64_t)kChunk + p] : 0xffffffffu;
+        rank[e] = p;
+    }
     for (int o = 0; o < nchunks; ++o) {
         if (o == q) continue;
         const int no = (int)min<int64_t>(kChunk, T - (int64_t)o * kChunk);
-        rank += lower_bound_pairs(wkey + (col + o) * (int64_t)kChunk, widx + (col + o) * (int64_t)kChunk, no, k, i);
+        __syncthreads();
+        for (int i = threadIdx.x; i < no; i += blockDim.x) {
+            okey[i] = wkey[(col + o) * (int64_t)kChunk + i];
+            oidx[i] = widx[(col + o) * (int64_t)kChunk + i];
+        }
+        __syncthreads();
+        // lower bound of the first element, then a forward walk for the others
+        int lo = 0, hi = no;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (pair_less(okey[mid], oidx[mid], mk[0], mi[0])) lo = mid + 1; else hi = mid;
+        }
+#pragma unroll
+        for (int e = 0; e < kPerThread; ++e) {
+            while (lo < no && pair_less(okey[lo], oidx[lo], mk[e], mi[e])) ++lo;
+            rank[e] += lo;
+        }
     }
-    const bool bad = nanflag[d * N + c] != 0;
-    double z = bad ? __builtin_nan("") : normal_score(rank + 1, T);
-    store_z<ZT>(Z, (d * T + (int64_t)i) * N + c, z);
+    __syncthreads();
+    const bool bad = sbad != 0;
+#pragma unroll
+    for (int e = 0; e < kPerThread; ++e) {
+        if (p0 + e < nq) {
+            const double z = bad ? __builtin_nan("") : normal_score(rank[e] + 1, T);
+            store_z<ZT>(Z, (d * T + (int64_t)mi[e]) * N + c, z);
+        }
+    }
 }
 
 __global__ void k_zero_i32(int32_t* p, int64_t n)
@@ -175,7 +199,7 @@ CopulaWs copula_layout(int64_t D, int64_t T, int64_t N)
         const size_t slots = (size_t)D * N * nchunks * kChunk;
         w.key_off = off; off = align_up(off + slots * 8, 256);
         w.idx_off = off; off = align_up(off + slots * 4, 256);
-        w.nan_off = off; off = align_up(off + (size_t)D * N * 4, 256);
+        w.nan_off = off; off = align_up(off + (size_t)D * N * nchunks * 4, 256);
     }
     w.total = off;
     return w;
@@ -196,12 +220,8 @@ thoi_status launch_copulize(const double* X, int64_t D, int64_t T, int64_t N, in
     uint32_t* widx = nchunks > 1 ? reinterpret_cast<uint32_t*>(base + w.idx_off) : nullptr;
     int32_t* nanf = nchunks > 1 ? reinterpret_cast<int32_t*>(base + w.nan_off) : nullptr;
 
-    // header and NaN flags start at zero (a fill kernel, so the call can be graph-captured)
+    // the header starts at zero (a fill kernel, so the call can be graph-captured)
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int32_t*>(hdr), (int64_t)(kWsHeader / 4));
-    if (nanf) {
-        const int64_t n = D * N;
-        hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024)), dim3(256), 0, s, nanf, n);
-    }
     if (D * N == 0 || T == 0) return hip_status(hipGetLastError());
 
     dim3 g1((unsigned)nchunks, (unsigned)N, (unsigned)D);
@@ -210,11 +230,13 @@ thoi_status launch_copulize(const double* X, int64_t D, int64_t T, int64_t N, in
     else
         hipLaunchKernelGGL(k_copula_sort<float>, g1, dim3(kSortThreads), 0, s, X, T, N, Z, wkey, widx, nanf, hdr);
     if (nchunks > 1) {
-        dim3 g2((unsigned)((kChunk + 255) / 256), (unsigned)nchunks, (unsigned)(N * D));
+        dim3 g2((unsigned)nchunks, (unsigned)(N * D));
         if (z_dtype == THOI_DTYPE_F64)
-            hipLaunchKernelGGL(k_copula_merge<double>, g2, dim3(256), 0, s, T, N, (int)nchunks, Z, wkey, widx, nanf);
+            hipLaunchKernelGGL(k_copula_merge<double>, g2, dim3(kSortThreads), 0, s, T, N, (int)nchunks, Z, wkey, widx,
+                               nanf, hdr);
         else
-            hipLaunchKernelGGL(k_copula_merge<float>, g2, dim3(256), 0, s, T, N, (int)nchunks, Z, wkey, widx, nanf);
+            hipLaunchKernelGGL(k_copula_merge<float>, g2, dim3(kSortThreads), 0, s, T, N, (int)nchunks, Z, wkey, widx,
+                               nanf, hdr);
     }
     return hip_status(hipGetLastError());
 }

@@ -19,22 +19,45 @@ constexpr int kSlab = 512;        // samples per workgroup
 template <typename ZT>
 __device__ __forceinline__ double ld_z(const void* Z, int64_t off) { return (double)static_cast<const ZT*>(Z)[off]; }
 
-// grid (ceil(N/64), D), block 256: column means, sequential FP64 sum per column.
+// grid (nslabs, D), block 256: per-slab column sums.  Thread t owns column t % N and every
+// (256 / N)-th row of the slab (N <= 256; wider matrices loop over column groups), so the loads
+// of a row are coalesced; the per-thread partials are added in a fixed order (reproducible).
 template <typename ZT>
-__global__ __launch_bounds__(256) void k_col_mean(const void* __restrict__ Z, int64_t T, int64_t N, double* __restrict__ mean)
+__global__ __launch_bounds__(256) void k_col_sums(const void* __restrict__ Z, int64_t T, int64_t N,
+                                                  double* __restrict__ part)
 {
-    __shared__ double part[4][64];
+    __shared__ double red[256];
     const int64_t d = blockIdx.y;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t c = blockIdx.x * 64 + lane;
-    double s = 0.0;
-    if (c < N) {
-        const int64_t t0 = (T * w) / 4, t1 = (T * (w + 1)) / 4;
-        for (int64_t t = t0; t < t1; ++t) s += ld_z<ZT>(Z, (d * T + t) * N + c);
+    const int slab = blockIdx.x, nslabs = gridDim.x;
+    const int64_t s0 = (int64_t)slab * kSlab, s1 = min<int64_t>(T, s0 + kSlab);
+    for (int64_t c0 = 0; c0 < N; c0 += 256) {
+        const int64_t nc = min<int64_t>(256, N - c0);
+        const int groups = (int)(256 / nc);
+        const int g = threadIdx.x / (int)nc, c = threadIdx.x % (int)nc;
+        double s = 0.0;
+        if (g < groups)
+            for (int64_t t = s0 + g; t < s1; t += groups) s += ld_z<ZT>(Z, (d * T + t) * N + c0 + c);
+        red[threadIdx.x] = s;
+        __syncthreads();
+        if (threadIdx.x < nc) {
+            double acc = 0.0;
+            for (int gg = 0; gg < groups; ++gg) acc += red[gg * nc + threadIdx.x];
+            part[((int64_t)d * nslabs + slab) * N + c0 + threadIdx.x] = acc;
+        }
+        __syncthreads();
     }
-    part[w][lane] = s;
-    __syncthreads();
-    if (w == 0 && c < N) mean[d * N + c] = (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]) / (double)T;
+}
+
+// grid (ceil(N/256), D), block 256: mean = (sum of the slab sums in slab order) / T.
+__global__ __launch_bounds__(256) void k_col_mean(const double* __restrict__ part, int nslabs, int64_t T, int64_t N,
+                                                  double* __restrict__ mean)
+{
+    const int64_t d = blockIdx.y;
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    double s = 0.0;
+    for (int sl = 0; sl < nslabs; ++sl) s += part[((int64_t)d * nslabs + sl) * N + c];
+    mean[d * N + c] = s / (double)T;
 }
 
 // grid (ntile_pairs, nslabs, D), block 64*kCovWaves.  partial: [D][nslabs][Np][Np].
@@ -102,8 +125,9 @@ size_t cov_ws_bytes(int64_t D, int64_t T, int64_t N)
     const int64_t Np = (N + 15) / 16 * 16;
     const int64_t nslabs = (T + kSlab - 1) / kSlab;
     size_t off = kWsHeader;
-    off = align_up(off + (size_t)D * N * 8, 256);
-    off = align_up(off + (size_t)D * nslabs * Np * Np * 8, 256);
+    off = align_up(off + (size_t)D * N * 8, 256);                      // means
+    off = align_up(off + (size_t)D * nslabs * N * 8, 256);             // slab column sums
+    off = align_up(off + (size_t)D * nslabs * Np * Np * 8, 256);       // slab products
     return off;
 }
 
@@ -113,18 +137,25 @@ thoi_status launch_cov(const void* Z, int32_t z_dtype, int64_t D, int64_t T, int
     const int64_t Np = (N + 15) / 16 * 16;
     const int64_t nslabs = (T + kSlab - 1) / kSlab;
     char* base = static_cast<char*>(ws);
-    double* mean = reinterpret_cast<double*>(base + kWsHeader);
-    double* partial = reinterpret_cast<double*>(base + align_up(kWsHeader + (size_t)D * N * 8, 256));
+    size_t off = kWsHeader;
+    double* mean = reinterpret_cast<double*>(base + off);
+    off = align_up(off + (size_t)D * N * 8, 256);
+    double* colsum = reinterpret_cast<double*>(base + off);
+    off = align_up(off + (size_t)D * nslabs * N * 8, 256);
+    double* partial = reinterpret_cast<double*>(base + off);
     if (D * N == 0) return THOI_OK;
-    dim3 gm((unsigned)((N + 63) / 64), (unsigned)D);
+    dim3 gs((unsigned)nslabs, (unsigned)D);
+    dim3 gm((unsigned)((N + 255) / 256), (unsigned)D);
     const int nt = (int)(Np / 16);
     dim3 gt((unsigned)(nt * (nt + 1) / 2), (unsigned)nslabs, (unsigned)D);
     dim3 gf((unsigned)((N * N + 255) / 256), (unsigned)D);
     if (z_dtype == THOI_DTYPE_F64) {
-        hipLaunchKernelGGL(k_col_mean<double>, gm, dim3(256), 0, s, Z, T, N, mean);
+        hipLaunchKernelGGL(k_col_sums<double>, gs, dim3(256), 0, s, Z, T, N, colsum);
+        hipLaunchKernelGGL(k_col_mean, gm, dim3(256), 0, s, colsum, (int)nslabs, T, N, mean);
         hipLaunchKernelGGL(k_cov_tiles<double>, gt, dim3(64 * kCovWaves), 0, s, Z, T, N, Np, mean, partial);
     } else {
-        hipLaunchKernelGGL(k_col_mean<float>, gm, dim3(256), 0, s, Z, T, N, mean);
+        hipLaunchKernelGGL(k_col_sums<float>, gs, dim3(256), 0, s, Z, T, N, colsum);
+        hipLaunchKernelGGL(k_col_mean, gm, dim3(256), 0, s, colsum, (int)nslabs, T, N, mean);
         hipLaunchKernelGGL(k_cov_tiles<float>, gt, dim3(64 * kCovWaves), 0, s, Z, T, N, Np, mean, partial);
     }
     hipLaunchKernelGGL(k_cov_finish, gf, dim3(256), 0, s, partial, (int)nslabs, T, N, Np, Sigma);

@@ -11,7 +11,7 @@ namespace {
 
 constexpr int kTile = 256;          // n-plets (= threads) per lane-engine tile
 constexpr int kMaxPieces = 24;      // orders per launch class
-constexpr int kWaveTileOut = 8;     // n-plets per wave-engine workgroup (output mode)
+constexpr int kWaveTileOut = 1;     // n-plets per wave-engine workgroup (output mode): spread the few, long factorisations over CUs
 constexpr int kWaveTileRed = 64;    // n-plets per wave-engine workgroup (reduce mode)
 constexpr int kListOrders = THOI_MAX_K + 2;   // k = 0..64 and one "invalid" bucket
 

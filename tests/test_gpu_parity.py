@@ -54,7 +54,10 @@ def assert_close(got, ref, atol, what):
 def test_copulize_one_and_many_chunks(env):
     torch, api, B, synth, orc = env
     for name, X in (("planted_10 T=1000", synth.planted_10()), ("latent_20 T=10000", synth.latent_20()),
-                    ("T=20000 N=3", np.random.default_rng(1).standard_normal((20000, 3)))):
+                    ("T=20000 N=3", np.random.default_rng(1).standard_normal((20000, 3))),
+                    ("T=1024 N=5", np.random.default_rng(4).standard_normal((1024, 5))),
+                    ("T=1025 N=5", np.random.default_rng(5).standard_normal((1025, 5))),
+                    ("T=2 N=2", np.array([[1.0, 3.0], [0.5, 3.0]]))):
         say(f"copulize {name}")
         Z = host(api.copulize(dev(torch, X)))
         Zo = orc.copula(X)
@@ -81,18 +84,20 @@ def test_copulize_batched_ties_signed_zero_f32(env):
 
 def test_copulize_nan_reported(env):
     torch, api, B, synth, orc = env
-    X = np.random.default_rng(3).standard_normal((500, 3))
-    X[17, 1] = np.nan
-    say("copulize with NaN")
-    with pytest.raises(B.ThoiError) as e:
-        api.copulize(dev(torch, X))
-    assert e.value.status == B.THOI_EINVAL_DATA
-    Z = host(api.copulize(dev(torch, X), check=False))
-    assert np.all(np.isnan(Z[:, 1])) and np.all(np.isfinite(Z[:, [0, 2]]))
+    for T, row in ((500, 17), (3000, 2999)):          # one chunk; several chunks, NaN in the ragged last one
+        X = np.random.default_rng(3).standard_normal((T, 3))
+        X[row, 1] = np.nan
+        say(f"copulize with NaN T={T}")
+        with pytest.raises(B.ThoiError) as e:
+            api.copulize(dev(torch, X))
+        assert e.value.status == B.THOI_EINVAL_DATA
+        Z = host(api.copulize(dev(torch, X), check=False))
+        assert np.all(np.isnan(Z[:, 1])) and np.all(np.isfinite(Z[:, [0, 2]]))
+        assert np.abs(Z[:, [0, 2]] - orc.copula(X[:, [0, 2]])).max() <= 1e-12 * 4
 
 
 # ------------------------------------------------------------------------------------------------ covariance
-@pytest.mark.parametrize("N,T", [(1, 2), (10, 1000), (20, 10000), (37, 513), (100, 2000)])
+@pytest.mark.parametrize("N,T", [(1, 2), (10, 1000), (20, 10000), (37, 513), (100, 2000), (300, 700)])
 def test_cov_matches_oracle(env, N, T):
     torch, api, B, synth, orc = env
     rng = np.random.default_rng(N * 7 + T)
