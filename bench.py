@@ -342,7 +342,9 @@ def main():
         t_step = t_gc + total / rate_pilot
         if 2 * t_step <= args.cpu_seconds:
             # the whole step fits the budget: repeat it (copula + covariance + all n-plets)
-            reps = max(1, int(round(args.cpu_seconds / t_step)))
+            t0 = time.perf_counter()                 # one whole step sets the repetition count
+            oracle.eval_list(oracle.gc_covariance(Xh), idx_all)
+            reps = max(1, int(round(args.cpu_seconds / (time.perf_counter() - t0))))
             t0 = time.perf_counter()
             for _ in range(reps):
                 Sig_c = oracle.gc_covariance(Xh)

@@ -61,10 +61,23 @@ __device__ __forceinline__ void stage_corr(const double* __restrict__ Sig, int N
         sLogd[j] = log(dj);
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-        const int i = e / N, j = e - i * N;
-        const double r = (i == j) ? (sIsd[i] == sIsd[i] ? 1.0 : __builtin_nan("")) : Sig[e] * sIsd[i] * sIsd[j];
-        sR[e] = (F)r;
+    // batches of 8 loads per thread in flight together (the loop is bound by memory round trips)
+    const int NN = N * N;
+    for (int e0 = threadIdx.x; e0 < NN; e0 += 8 * blockDim.x) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * (int)blockDim.x;
+            v[u] = e < NN ? Sig[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * (int)blockDim.x;
+            if (e < NN) {
+                const int i = e / N, j = e - i * N;
+                sR[e] = (F)((i == j) ? (sIsd[i] == sIsd[i] ? 1.0 : __builtin_nan("")) : v[u] * sIsd[i] * sIsd[j]);
+            }
+        }
     }
     __syncthreads();
 }

@@ -524,18 +524,25 @@ void launch_engines(EvalArgs& a, const Plan& P, const RedArgs& red, hipStream_t 
     const KClass* cls = classes_for<F>(ncls);
     const bool reduce = red.active != 0;
     const int N = a.N;
+    // the class launches are independent: fan them out over side streams
+    int nl = P.wblk ? 1 : 0;
+    for (int c = 0; c < ncls; ++c) nl += P.nblk[c] != 0;
+    FanScope fan(s, nl);
+    int b = 0;
     for (int c = 0; c < ncls; ++c) {
         if (P.nblk[c] == 0) continue;
         const int kb = MODE == THOI_SEL_RANGE ? cls[c].hi : 0;
         const size_t lds = lane_stage_bytes(N, kb, sizeof(F)) + red_lds(reduce);
         const LaneKernel kern = lane_kernel<F, MODE>(c, reduce);
-        hipLaunchKernelGGL(kern, dim3((unsigned)P.nblk[c], (unsigned)a.D), dim3(kTile), lds, s, a, P.tabs[c], red);
+        hipLaunchKernelGGL(kern, dim3((unsigned)P.nblk[c], (unsigned)a.D), dim3(kTile), lds, fan.stream(b++), a,
+                           P.tabs[c], red);
     }
     if (P.wblk) {
         const int klo = MODE == THOI_SEL_RANGE ? 0 : lane_max_for(a.precision) + 1;
         const size_t lds = wave_stage_bytes(N, P.wkmax, MODE == THOI_SEL_RANGE) + red_lds(reduce);
         const WaveKernel wk = wave_kernel<MODE>(reduce);
-        hipLaunchKernelGGL(wk, dim3((unsigned)P.wblk, (unsigned)a.D), dim3(64), lds, s, a, P.wtab, red, klo, P.wkmax);
+        hipLaunchKernelGGL(wk, dim3((unsigned)P.wblk, (unsigned)a.D), dim3(64), lds, fan.stream(b++), a, P.wtab, red,
+                           klo, P.wkmax);
     }
 }
 

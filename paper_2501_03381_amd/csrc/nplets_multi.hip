@@ -370,12 +370,16 @@ void launch_multi_chunk(EvalArgs& a, const MultiChunk& ch, const MultiPlan* plan
     const bool reduce = red.active != 0;
     int ncls = 0;
     const KClass* cls = classes_for<F>(ncls);
+    int nl = 0;
+    for (int c = 0; c < ncls; ++c) nl += cls_units_host[c] != 0;
+    FanScope fan(s, nl);       // the class launches are independent
+    int b = 0;
     for (int c = 0; c < ncls; ++c) {
         if (cls_units_host[c] == 0) continue;
         const int64_t G = grid_blocks > 0 ? grid_blocks : (cls_units_host[c] < 2048 ? cls_units_host[c] : 2048);
         const size_t lds = lane_stage_bytes(ch.nmax, cls[c].hi, sizeof(F)) + red_lds(reduce);
         const MultiKernel kern = reduce ? multi_kernel_r<F, true>(c) : multi_kernel_r<F, false>(c);
-        hipLaunchKernelGGL(kern, dim3((unsigned)G), dim3(kTile), lds, s, a, plan, ch, c, red);
+        hipLaunchKernelGGL(kern, dim3((unsigned)G), dim3(kTile), lds, fan.stream(b++), a, plan, ch, c, red);
     }
 }
 

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "thoi.h"
 
 namespace thoi {
@@ -39,6 +41,24 @@ uint64_t binom_u64(int n, int m);
 void bias_offsets(int k, int T, double* d_tc, double* d_dtc, double* eta);
 // psi((T-1)/2) and psi((T-2)/2), the seeds of the device-side recurrence for the offsets.
 void bias_psi_seeds(int T, double* psi1, double* psi2);
+
+// Fork/join over per-device side streams for independent launches (see fan.cpp).  Branch 0 is the
+// caller's stream; branches beyond the side streams wrap around.
+constexpr int kFanSide = 6;
+class FanScope {
+public:
+    FanScope(hipStream_t s, int branches);
+    ~FanScope();
+    FanScope(const FanScope&) = delete;
+    FanScope& operator=(const FanScope&) = delete;
+    hipStream_t stream(int branch) const;
+
+private:
+    hipStream_t s_;
+    void* fan_ = nullptr;
+    int nside_ = 0;
+    std::unique_lock<std::mutex> lock_;
+};
 
 // Launchers implemented in the kernel translation units.
 thoi_status launch_copulize(const double* X, int64_t D, int64_t T, int64_t N, int32_t z_dtype, void* Z,
