@@ -26,6 +26,30 @@ METRIC = "n-plets/s (Ω,S,TC,DTC) at N=20 all orders; FP32+refine vs FP64, same 
 PEAK_FP32_PUBLISHED = 157.3      # TFLOP/s, MI355X vector FP32 (counts packed FP32)
 PEAK_FP32_SCALAR = 78.6          # TFLOP/s, 256 CU x 64 FMA/clk x 2 flop x 2.4 GHz (packed FP32 disabled)
 PEAK_FP64 = 78.6
+# HBM traffic of the dominant launch, from two hardware-counter runs (profiles/); valid while the
+# kernel sources hash to the value recorded with it
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "eval_lane_f32_o9-12_latent20_traffic.json")
+KERNEL_SOURCES = ["include/thoi.h"] + [f"paper_2501_03381_amd/csrc/{f}" for f in (
+    "thoi_internal.hpp", "nplets_common.hpp", "reduce_common.hpp", "nplets_fwd_common.hpp", "nplets_fwd.hip")]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic():
+    """Bytes per launch of the dominant kernel from the counter runs, or None if stale/missing."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    return rec["traffic_bytes_per_launch"] if rec.get("source_sha256") == kernel_source_hash() else None
 
 
 def flops(k: int) -> int:
@@ -316,7 +340,7 @@ def main():
     roofline = {
         "bound": "alu", "kernel": "k_eval_lane<float,9,12,RANGE>", "achieved": round(achieved, 3),
         "peak": PEAK_FP32_PUBLISHED, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_PUBLISHED, 4),
-        "traffic": None,
+        "traffic": stored_traffic(), "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "peak_scalar_fp32": PEAK_FP32_SCALAR, "frac_scalar_fp32": round(achieved / PEAK_FP32_SCALAR, 4),
         "launch_us": round(dur_ms * 1e3, 2), "nplets_per_launch": cls_nplets, "flops_per_launch": cls_flops,
     }

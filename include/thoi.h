@@ -149,6 +149,7 @@ thoi_status thoi_copulize(const double* X, int64_t D, int64_t T, int64_t N, int3
  * accumulated in FP64 on the matrix cores.
  *   Z: device [D][T][N] (z_dtype).  Sigma: device [D][N][N] FP64 (overwritten).
  *   ws: device, >= thoi_workspace_bytes(THOI_WS_COV, D, T, N, NULL, NULL).
+ * Requires 2 <= T <= 2^31 - 1, N <= 4096, D <= 65535 (else THOI_EUNSUPPORTED).
  */
 thoi_status thoi_cov(const void* Z, int32_t z_dtype, int64_t D, int64_t T, int64_t N,
                      double* Sigma, void* ws, size_t ws_bytes, void* stream);

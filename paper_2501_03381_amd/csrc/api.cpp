@@ -203,7 +203,7 @@ thoi_status thoi_cov(const void* Z, int32_t z_dtype, int64_t D, int64_t T, int64
                      size_t ws_bytes, void* stream)
 {
     if (D < 0 || N < 1 || T < 2 || !valid_dtype(z_dtype)) return THOI_EINVAL;
-    if (D > 65535 || N > 4096 || T > ((int64_t)1 << 40)) return THOI_EUNSUPPORTED;
+    if (D > 65535 || N > 4096 || T > INT32_MAX) return THOI_EUNSUPPORTED;
     if (D > 0 && (!Z || !Sigma)) return THOI_EINVAL;
     const size_t need = cov_ws_bytes(D, T, N);
     if (!ws || ws_bytes < need) return THOI_EWORKSPACE;

@@ -3,10 +3,9 @@
 // replaced by Phi^{-1}(r / (T+1)), r its 1-based ordinal rank, equal values ranked by sample
 // index.
 //
-// Design: a column is cut into chunks of kChunk samples.  One workgroup sorts one chunk of
-// (orderable key, sample index) pairs with a bitonic network held in registers (four pairs per
-// thread): partners inside a wavefront are exchanged by cross-lane shuffles, only the two largest
-// distances go through LDS.  With a single chunk the sorted position is the rank.  Otherwise the
+// Design: a column is cut into chunks of kChunk samples.  One workgroup of kChunk threads sorts
+// one chunk of (orderable key, sample index) pairs with a bitonic network held in registers:
+// partners inside a wavefront are exchanged by cross-lane shuffles, larger distances through LDS.  With a single chunk the sorted position is the rank.  Otherwise the
 // sorted chunks go to the workspace and a merge workgroup per chunk adds, for each of its
 // elements, the number of entries before it in every chunk of the column (its own included).
 // Every kernel issues its global loads in batches, all in flight together: at these sizes the
@@ -17,9 +16,9 @@ namespace thoi {
 namespace {
 
 constexpr int kChunk = 1024;                       // samples per sorted chunk
-constexpr int kSortThreads = 256;
-constexpr int kSortReg = kChunk / kSortThreads;    // elements per thread in the sort
-constexpr int kMergeThreads = 256;
+constexpr int kSortThreads = 1024;
+constexpr int kSortReg = kChunk / kSortThreads;    // elements per thread in the sort (one)
+constexpr int kMergeThreads = 1024;
 constexpr int kMergeReg = kChunk / kMergeThreads;  // elements per thread in the merge
 constexpr int kMergeStage = 7;                     // chunks staged in LDS at a time (56 KB of values)
 
@@ -198,8 +197,14 @@ __global__ __launch_bounds__(kMergeThreads) void k_copula_merge(int64_t T, int64
 {
     __shared__ uint64_t okey[kMergeStage][kChunk];
     const int tid = threadIdx.x;
-    const int q = blockIdx.x;
-    const int64_t c = blockIdx.y % N, d = blockIdx.y / N;
+    // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs; give consecutive work items
+    // (the chunks of one column, which read the same staged chunks) to the same XCD
+    const int64_t G = (int64_t)gridDim.x * gridDim.y, b = blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
+    const int64_t xcd = b % 8, q8 = G / 8, r8 = G % 8;
+    const int64_t w = xcd * q8 + (xcd < r8 ? xcd : r8) + b / 8;
+    const int q = (int)(w % nchunks);
+    const int64_t cd = w / nchunks;
+    const int64_t c = cd % N, d = cd / N;
     const int64_t col = (d * N + c) * nchunks;
     const int nq = (int)min<int64_t>(kChunk, T - (int64_t)q * kChunk);
     int f = 0;

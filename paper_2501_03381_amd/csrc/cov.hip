@@ -23,7 +23,7 @@ constexpr int kStageLd = kSlab * 32 / kCovThreads;   // staged values per thread
 template <typename ZT>
 __device__ __forceinline__ double ld_z(const void* Z, int64_t off) { return (double)static_cast<const ZT*>(Z)[off]; }
 
-// grid (ntile_pairs, nslabs, D), block kCovThreads.
+// grid (nslabs, ntile_pairs, D), block kCovThreads.
 // partial: [D][nslabs][Np][Np] centred slab products; smean: [D][nslabs][N] slab means (written by
 // the diagonal tiles, which are the only blocks covering each column once).
 template <typename ZT>
@@ -35,10 +35,10 @@ __global__ __launch_bounds__(kCovThreads) void k_cov_slab(const void* __restrict
     __shared__ double red[4][256];
     __shared__ double mcol[32];
     const int64_t d = blockIdx.z;
-    const int slab = blockIdx.y, nslabs = gridDim.y;
+    const int slab = blockIdx.x, nslabs = gridDim.x;
     // tile pair index -> (ta, tb) with ta <= tb
     const int nt = (int)(Np / 16);
-    int p = blockIdx.x, ta = 0;
+    int p = blockIdx.y, ta = 0;
     while (p >= nt - ta) { p -= nt - ta; ++ta; }
     const int tb = ta + p;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -162,7 +162,7 @@ thoi_status launch_cov(const void* Z, int32_t z_dtype, int64_t D, int64_t T, int
     double* partial = reinterpret_cast<double*>(base + off);
     if (D * N == 0) return THOI_OK;
     const int nt = (int)(Np / 16);
-    dim3 gt((unsigned)(nt * (nt + 1) / 2), (unsigned)nslabs, (unsigned)D);
+    dim3 gt((unsigned)nslabs, (unsigned)(nt * (nt + 1) / 2), (unsigned)D);
     dim3 gf((unsigned)((N * (N + 1) / 2 + 3) / 4), (unsigned)D);
     if (z_dtype == THOI_DTYPE_F64)
         hipLaunchKernelGGL(k_cov_slab<double>, gt, dim3(kCovThreads), 0, s, Z, T, N, Np, smean, partial);

@@ -27,7 +27,8 @@ __global__ __launch_bounds__(kTile) void k_eval_lane(EvalArgs a, PieceTable tab,
     const int N = a.N;
     const int d = blockIdx.y;
     const int64_t blk = blockIdx.x;
-    const int64_t per_blk = (int64_t)kTile * a.seg_tiles;
+    constexpr int S = lane_per_thread<F>(KHI, MODE);
+    const int64_t per_blk = (int64_t)kTile * S * a.seg_tiles;
     // which order / piece does this workgroup belong to (uniform in the workgroup)
     int k = -1;
     int64_t first = 0, pos0 = 0, cnt = 0, blk0 = 0;
@@ -54,12 +55,12 @@ __global__ __launch_bounds__(kTile) void k_eval_lane(EvalArgs a, PieceTable tab,
     double* sIsd = reinterpret_cast<double*>(smem + off);
     double* sLogd = sIsd + N;
     uint64_t* sBin = reinterpret_cast<uint64_t*>(sLogd + N);
-    RedLds& S = *reinterpret_cast<RedLds*>(smem + lane_stage_bytes(N, kb, sizeof(F)));
+    RedLds& Rl = *reinterpret_cast<RedLds*>(smem + lane_stage_bytes(N, kb, sizeof(F)));
     if (threadIdx.x == 0) bias_for(a.bias, k, sbias[0], sbias[1], sbias[2]);
     if constexpr (MODE == THOI_SEL_RANGE) stage_binomials(N, kb, sBin);
     stage_corr<F>(a.Sigma + (int64_t)d * N * N, N, sR, sIsd, sLogd);
     constexpr bool reduce = RED;
-    if constexpr (RED) red_begin(S, red.topk, red.bins);
+    if constexpr (RED) red_begin(Rl, red.topk, red.bins);
 
     LaneCtx cx;
     cx.d = d;
@@ -73,16 +74,19 @@ __global__ __launch_bounds__(kTile) void k_eval_lane(EvalArgs a, PieceTable tab,
     cx.eta = sbias[2];
     const int64_t base = (blk - blk0) * per_blk;
     for (int t = 0; t < a.seg_tiles; ++t) {
-        const int64_t tb = base + (int64_t)t * kTile;
+        const int64_t tb = base + (int64_t)t * kTile * S;
         if (tb >= cnt) break;                         // uniform: same for the whole workgroup
-        cx.local = tb + threadIdx.x;
-        double omega = 0.0;
-        int64_t gidx = 0;
-        bool valid = false;
-        if (cx.local < cnt) valid = dispatch_k<F, KLO, KHI, MODE>(k, a, cx, sR, sLogd, sBin, omega, gidx);
-        if constexpr (RED) red_push(S, red, k, valid, omega, gidx);
+        cx.local = tb + (int64_t)S * threadIdx.x;
+        double omega[S] = {};
+        int64_t gidx[S] = {};
+        bool valid[S] = {};
+        if (cx.local < cnt) dispatch_k<F, KLO, KHI, MODE, S>(k, a, cx, sR, sLogd, sBin, cnt, omega, gidx, valid);
+        if constexpr (RED) {
+#pragma unroll
+            for (int j = 0; j < S; ++j) red_push(Rl, red, k, valid[j], omega[j], gidx[j]);
+        }
     }
-    if constexpr (RED) red_end(S, red, a.hdr, d, k);
+    if constexpr (RED) red_end(Rl, red, a.hdr, d, k);
 }
 
 template <int MODE, bool RED>
@@ -396,7 +400,7 @@ Plan make_plan(int N, const thoi_nplets* sel, bool reduce, int precision, int se
         if (P.seg_tiles < 1) P.seg_tiles = 1;
     }
     if (seg_tiles_hint > 0) P.seg_tiles = seg_tiles_hint;
-    const int64_t per_blk = (int64_t)kTile * P.seg_tiles;
+    const int64_t per_blk = (int64_t)kTile * P.seg_tiles;     // one n-plet per lane (index lists)
     if (sel->mode == THOI_SEL_RANGE) {
         int64_t g = 0;
         const int64_t gb = sel->g_begin, ge = sel->g_begin + sel->g_count;
@@ -411,8 +415,9 @@ Plan make_plan(int N, const thoi_nplets* sel, bool reduce, int precision, int se
                 p.cnt = hi - lo;
                 if (k <= lane_max) {
                     const int c = class_of<F>(k);
+                    const int64_t pb = per_blk * lane_per_thread<F>(cls[c].hi, THOI_SEL_RANGE);
                     p.blk0 = P.nblk[c];
-                    P.nblk[c] += (p.cnt + per_blk - 1) / per_blk;
+                    P.nblk[c] += (p.cnt + pb - 1) / pb;
                     P.tabs[c].p[P.tabs[c].n++] = p;
                 } else {
                     p.blk0 = P.wblk;

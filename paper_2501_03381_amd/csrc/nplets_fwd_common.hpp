@@ -164,33 +164,26 @@ struct LaneCtx {
     double dtc, ddtc, eta;
 };
 
-template <typename F, int K, int MODE>
-__device__ __forceinline__ bool lane_task(const EvalArgs& a, const LaneCtx& cx, const F* sR, const double* sLogd,
-                                          const uint64_t* sBin, double& omega, int64_t& gidx)
+// Next combination of the same order in lexicographic order (the caller knows it exists):
+// the last index that can still grow grows by one and the indices after it follow it.
+template <int K>
+__device__ __forceinline__ void next_lex(int (&c)[K > 0 ? K : 1], int N)
 {
-    int c[K > 0 ? K : 1];
-    int64_t pos;
-    if constexpr (MODE == THOI_SEL_RANGE) {
-        unrank_lex<K>((uint64_t)(cx.first + cx.local), cx.N, sBin, cx.kb, c);
-        pos = cx.pos0 + cx.local;
-        gidx = a.g_begin + pos;
-    } else if constexpr (MODE == kSelMulti) {
-        unrank_lex<K>((uint64_t)(cx.first + cx.local), cx.N, sBin, cx.kb, c);
-        pos = cx.pos0 + cx.local;
-        gidx = cx.gbase + cx.local;
-    } else if constexpr (MODE == THOI_SEL_LIST) {
-        pos = a.perm[cx.first + cx.local];
-        gidx = pos;
-        const int32_t* row = a.idx + pos * a.kmax_list;
+    if constexpr (K > 0) {
+        int piv = 0;
 #pragma unroll
-        for (int i = 0; i < K; ++i) c[i] = row[i];
-    } else {
-        pos = a.perm[cx.first + cx.local];
-        gidx = pos;
-        uint64_t m = a.mask[pos];
+        for (int i = 0; i < K; ++i) piv = c[i] < N - K + i ? i : piv;
+        c[0] += piv == 0 ? 1 : 0;
 #pragma unroll
-        for (int i = 0; i < K; ++i) { c[i] = __builtin_ctzll(m); m &= m - 1; }
+        for (int i = 1; i < K; ++i) c[i] = i == piv ? c[i] + 1 : (i > piv ? c[i - 1] + 1 : c[i]);
     }
+}
+
+// Factor one n-plet of order K and store (or hand back) its measures.
+template <typename F, int K>
+__device__ __forceinline__ bool lane_eval(const EvalArgs& a, const LaneCtx& cx, const F* sR, const double* sLogd,
+                                          const int (&c)[K > 0 ? K : 1], int64_t pos, double& omega)
+{
     const FactorOut<F> f = lane_factor<F, K>(c, sR, cx.N);
     double sumlogd = 0.0;
     if (a.write_H) {
@@ -200,13 +193,59 @@ __device__ __forceinline__ bool lane_task(const EvalArgs& a, const LaneCtx& cx, 
     return store_result<F>(a, cx.reduce, cx.d, pos, K, f, sumlogd, cx.dtc, cx.ddtc, cx.eta, false, omega);
 }
 
-template <typename F, int K, int KHI, int MODE>
-__device__ __forceinline__ bool dispatch_k(int k, const EvalArgs& a, const LaneCtx& cx, const F* sR,
-                                           const double* sLogd, const uint64_t* sBin, double& omega, int64_t& gidx)
+// S consecutive n-plets of one lane, starting at cx.local inside the piece (cnt n-plets).  In
+// lexicographic modes the first is unranked and the others follow by next_lex, so the unranking
+// is paid once per S n-plets.
+template <typename F, int K, int MODE, int S>
+__device__ __forceinline__ void lane_task(const EvalArgs& a, const LaneCtx& cx, const F* sR, const double* sLogd,
+                                          const uint64_t* sBin, int64_t cnt, double (&omega)[S],
+                                          int64_t (&gidx)[S], bool (&valid)[S])
 {
-    if (k == K) return lane_task<F, K, MODE>(a, cx, sR, sLogd, sBin, omega, gidx);
-    if constexpr (K < KHI) return dispatch_k<F, K + 1, KHI, MODE>(k, a, cx, sR, sLogd, sBin, omega, gidx);
-    return false;
+    int c[K > 0 ? K : 1];
+    if constexpr (MODE == THOI_SEL_RANGE || MODE == kSelMulti) {
+        unrank_lex<K>((uint64_t)(cx.first + cx.local), cx.N, sBin, cx.kb, c);
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            if (j > 0) {
+                if (cx.local + j >= cnt) break;
+                next_lex<K>(c, cx.N);
+            }
+            const int64_t pos = cx.pos0 + cx.local + j;
+            gidx[j] = MODE == THOI_SEL_RANGE ? a.g_begin + pos : cx.gbase + cx.local + j;
+            valid[j] = lane_eval<F, K>(a, cx, sR, sLogd, c, pos, omega[j]);
+        }
+    } else {
+        static_assert(S == 1, "index lists are evaluated one n-plet per lane");
+        const int64_t pos = a.perm[cx.first + cx.local];
+        gidx[0] = pos;
+        if constexpr (MODE == THOI_SEL_LIST) {
+            const int32_t* row = a.idx + pos * a.kmax_list;
+#pragma unroll
+            for (int i = 0; i < K; ++i) c[i] = row[i];
+        } else {
+            uint64_t m = a.mask[pos];
+#pragma unroll
+            for (int i = 0; i < K; ++i) { c[i] = __builtin_ctzll(m); m &= m - 1; }
+        }
+        valid[0] = lane_eval<F, K>(a, cx, sR, sLogd, c, pos, omega[0]);
+    }
+}
+
+template <typename F, int K, int KHI, int MODE, int S>
+__device__ __forceinline__ void dispatch_k(int k, const EvalArgs& a, const LaneCtx& cx, const F* sR,
+                                           const double* sLogd, const uint64_t* sBin, int64_t cnt,
+                                           double (&omega)[S], int64_t (&gidx)[S], bool (&valid)[S])
+{
+    if (k == K) lane_task<F, K, MODE, S>(a, cx, sR, sLogd, sBin, cnt, omega, gidx, valid);
+    else if constexpr (K < KHI) dispatch_k<F, K + 1, KHI, MODE, S>(k, a, cx, sR, sLogd, sBin, cnt, omega, gidx, valid);
+}
+
+// n-plets per lane in the lane engine: two in RANGE mode where the class leaves register room
+// for the index set carried from one to the next, else one.
+template <typename F>
+__host__ __device__ constexpr int lane_per_thread(int khi, int mode)
+{
+    return mode == THOI_SEL_RANGE && khi <= (sizeof(F) == 4 ? 16 : 10) ? 2 : 1;
 }
 
 // LDS: sR [N*N] F | sIsd [N] f64 | sLogd [N] f64 | sBin [N*kb] u64 | (reduce) RedLds

@@ -201,11 +201,11 @@ __global__ __launch_bounds__(kTile) void k_eval_multi(EvalArgs a, const MultiPla
         const int64_t base = (u - U.unit0) * ch.per_unit;
         for (int64_t tb = base; tb < base + ch.per_unit && tb < U.cnt; tb += kTile) {
             cx.local = tb + threadIdx.x;
-            double omega = 0.0;
-            int64_t gidx = 0;
-            bool valid = false;
-            if (cx.local < U.cnt) valid = dispatch_k<F, KLO, KHI, kSelMulti>(U.k, a, cx, sR, sLogd, sBin, omega, gidx);
-            if constexpr (RED) red_push(S, red, U.k, valid, omega, gidx);
+            double omega[1] = {0.0};
+            int64_t gidx[1] = {0};
+            bool valid[1] = {false};
+            if (cx.local < U.cnt) dispatch_k<F, KLO, KHI, kSelMulti, 1>(U.k, a, cx, sR, sLogd, sBin, U.cnt, omega, gidx, valid);
+            if constexpr (RED) red_push(S, red, U.k, valid[0], omega[0], gidx[0]);
         }
         if constexpr (RED) red_end(S, red, a.hdr, U.d, U.k);
         __syncthreads();
