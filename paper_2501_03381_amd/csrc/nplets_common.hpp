@@ -47,55 +47,85 @@ template <typename F> struct LogProd {
     __device__ __forceinline__ F log() const { return (Num<F>::log2m(Num<F>::mant(m)) + F(e + Num<F>::expo(m))) * F(kLn2); }
 };
 
+// Pascal's triangle C(n, m), n, m < 64, exact in uint64 (C(63, 31) < 2^60), built at compile time.
+struct PascalTable {
+    uint64_t v[64][64];
+};
+constexpr PascalTable make_pascal()
+{
+    PascalTable t{};
+    for (int n = 0; n < 64; ++n)
+        for (int m = 0; m < 64; ++m)
+            t.v[n][m] = m == 0 ? 1ull : (n == 0 ? 0ull : t.v[n - 1][m - 1] + t.v[n - 1][m]);
+    return t;
+}
+__device__ constexpr PascalTable kPascal = make_pascal();
+
 // ------------------------------------------------------------------------------------------------
-// Staging of one dataset into LDS: R (precision F) and log Sigma_jj (FP64).
-// Must be called by the whole block; ends with a barrier.
+// Staging of one dataset into LDS: R (precision F), 1/sqrt(Sigma_jj) and log Sigma_jj (FP64).
+// Must be called by the whole block; ends with a barrier.  Every thread loads the entries it
+// writes together with the two variances they are scaled by, in batches of 8 entries whose loads
+// are all in flight at once: the whole staging is one round trip to memory.
 // ------------------------------------------------------------------------------------------------
+// With sBin, the block also copies C(n, m), n < N, m < kb, into sBin[n * kb + m]; the first
+// entries' loads go out with the correlation loads.
 template <typename F>
 __device__ __forceinline__ void stage_corr(const double* __restrict__ Sig, int N, F* __restrict__ sR,
-                                           double* __restrict__ sIsd, double* __restrict__ sLogd)
+                                           double* __restrict__ sIsd, double* __restrict__ sLogd,
+                                           uint64_t* __restrict__ sBin = nullptr, int kb = 0)
 {
-    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    const int NN = N * N;
+    const int bd = (int)blockDim.x;
+    const int nbin = sBin ? N * kb : 0;
+    const uint64_t b0 = (int)threadIdx.x < nbin ? kPascal.v[threadIdx.x / kb][threadIdx.x % kb] : 0ull;
+    for (int e0 = threadIdx.x; e0 < NN; e0 += 8 * bd) {
+        double v[8], di[8], dj[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * bd;
+            const int i = e / N, j = e - i * N;
+            v[u] = e < NN ? Sig[e] : 0.0;
+            di[u] = e < NN ? Sig[(int64_t)i * N + i] : 1.0;
+            dj[u] = e < NN ? Sig[(int64_t)j * N + j] : 1.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * bd;
+            if (e < NN) {
+                const int i = e / N, j = e - i * N;
+                const double si = di[u] > 0.0 ? 1.0 / sqrt(di[u]) : __builtin_nan("");
+                const double sj = dj[u] > 0.0 ? 1.0 / sqrt(dj[u]) : __builtin_nan("");
+                sR[e] = (F)((i == j) ? (si == si ? 1.0 : __builtin_nan("")) : v[u] * si * sj);
+            }
+        }
+    }
+    for (int j = threadIdx.x; j < N; j += bd) {
         const double dj = Sig[(int64_t)j * N + j];
         sIsd[j] = dj > 0.0 ? 1.0 / sqrt(dj) : __builtin_nan("");
         sLogd[j] = log(dj);
     }
-    __syncthreads();
-    // batches of 8 loads per thread in flight together (the loop is bound by memory round trips)
-    const int NN = N * N;
-    for (int e0 = threadIdx.x; e0 < NN; e0 += 8 * blockDim.x) {
-        double v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * (int)blockDim.x;
-            v[u] = e < NN ? Sig[e] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * (int)blockDim.x;
-            if (e < NN) {
-                const int i = e / N, j = e - i * N;
-                sR[e] = (F)((i == j) ? (sIsd[i] == sIsd[i] ? 1.0 : __builtin_nan("")) : v[u] * sIsd[i] * sIsd[j]);
-            }
-        }
-    }
+    if ((int)threadIdx.x < nbin) sBin[threadIdx.x] = b0;
+    for (int e = threadIdx.x + bd; e < nbin; e += bd) sBin[e] = kPascal.v[e / kb][e % kb];
     __syncthreads();
 }
 
-// Pascal's triangle C(n, m), n < N, m < kb, into LDS (row stride kb <= 64), computed by wave 0
-// with lane m holding column m.  Caller synchronises afterwards.
+// C(n, m), n < N, m < kb, into LDS at [n * kb + m] (kb <= 64), copied from the compile-time table
+// with all loads of a thread in flight together.  Caller synchronises afterwards.
 __device__ __forceinline__ void stage_binomials(int N, int kb, uint64_t* __restrict__ sBin)
 {
-    if (threadIdx.x < 64) {
-        const int m = threadIdx.x;
-        uint64_t v = (m == 0) ? 1ull : 0ull;   // row n = 0
-        for (int n = 0; n < N; ++n) {
-            if (n > 0) {
-                const uint32_t lo = __shfl_up((uint32_t)v, 1, 64);
-                const uint32_t hi = __shfl_up((uint32_t)(v >> 32), 1, 64);
-                if (m > 0) v += ((uint64_t)hi << 32) | lo;
-            }
-            if (m < kb) sBin[n * kb + m] = v;
+    const int tot = N * kb;
+    const int bd = (int)blockDim.x;
+    for (int e0 = threadIdx.x; e0 < tot; e0 += 8 * bd) {
+        uint64_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * bd;
+            v[u] = e < tot ? kPascal.v[e / kb][e % kb] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * bd;
+            if (e < tot) sBin[e] = v[u];
         }
     }
 }
@@ -107,6 +137,28 @@ __device__ __forceinline__ void unrank_lex(uint64_t r, int N, const uint64_t* __
                                            int (&c)[K > 0 ? K : 1])
 {
     int x = 0;
+    if (N <= 33) {
+        // every C(n, m) with n < 33 fits in 32 bits: walk the low words of the table
+        const uint32_t* b32 = reinterpret_cast<const uint32_t*>(sBin);
+        uint32_t rr = (uint32_t)r;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int m = K - 1 - i;
+            if (m == 0) {
+                c[i] = x + (int)rr;
+            } else {
+                while (x < N) {
+                    const uint32_t b = b32[2 * ((N - 1 - x) * kb + m)];
+                    if (rr < b) break;
+                    rr -= b;
+                    ++x;
+                }
+                c[i] = x;
+                ++x;
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const int m = K - 1 - i;
@@ -174,16 +226,16 @@ __device__ __forceinline__ FactorOut<F> lane_factor(const int (&c)[K > 0 ? K : 1
         for (int j = 0; j < i; ++j) a[tri(i, j)] = row[c[j]];
         a[tri(i, i)] = F(1);
     }
-    F inv[K > 0 ? K : 1];
     LogProd<F> det;
     bool ok = true;
-    // right-looking Cholesky, L overwrites the lower triangle; inv[j] = 1 / L_jj
+    // right-looking Cholesky, L overwrites the strict lower triangle and the diagonal slot j
+    // keeps 1 / L_jj (the pivot itself is not needed again)
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const F p = a[tri(j, j)];
         ok = ok && (p > F(0));
         const F r = Num<F>::rsq(p);
-        inv[j] = r;
+        a[tri(j, j)] = r;
         det.mul(p);
         if ((j & 3) == 3) det.renorm();
 #pragma unroll
@@ -201,14 +253,14 @@ __device__ __forceinline__ FactorOut<F> lane_factor(const int (&c)[K > 0 ? K : 1
     F vmax = F(0);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        const F wjj = inv[j];
+        const F wjj = a[tri(j, j)];
         F acc = wjj * wjj;
 #pragma unroll
         for (int i = j + 1; i < K; ++i) {
             F s = a[tri(i, j)] * wjj;
 #pragma unroll
             for (int m = j + 1; m < i; ++m) s += a[tri(i, m)] * a[tri(m, j)];
-            const F w = -s * inv[i];
+            const F w = -s * a[tri(i, i)];
             a[tri(i, j)] = w;
             acc += w * w;
         }

@@ -57,8 +57,7 @@ __global__ __launch_bounds__(kTile) void k_eval_lane(EvalArgs a, PieceTable tab,
     uint64_t* sBin = reinterpret_cast<uint64_t*>(sLogd + N);
     RedLds& Rl = *reinterpret_cast<RedLds*>(smem + lane_stage_bytes(N, kb, sizeof(F)));
     if (threadIdx.x == 0) bias_for(a.bias, k, sbias[0], sbias[1], sbias[2]);
-    if constexpr (MODE == THOI_SEL_RANGE) stage_binomials(N, kb, sBin);
-    stage_corr<F>(a.Sigma + (int64_t)d * N * N, N, sR, sIsd, sLogd);
+    stage_corr<F>(a.Sigma + (int64_t)d * N * N, N, sR, sIsd, sLogd, MODE == THOI_SEL_RANGE ? sBin : nullptr, kb);
     constexpr bool reduce = RED;
     if constexpr (RED) red_begin(Rl, red.topk, red.bins);
 
