@@ -68,7 +68,7 @@ def parse():
     p.add_argument("--skip-fp64", action="store_true")
     p.add_argument("--no-saturated", action="store_true", help="skip the 64-replica saturation run")
     p.add_argument("--workload", default="latent20",
-                   choices=["latent20", "ar1_30", "uneven1024", "latent100_grad", "classes", "greedy100"],
+                   choices=["latent20", "ar1_30", "uneven1024", "latent100_grad", "classes", "greedy100", "anneal100"],
                    help="latent20: the headline N=20 step (default); the others time the remaining "
                         "configurations of the method (one JSON line each)")
     p.add_argument("--profile-kernels", action="store_true",
@@ -291,6 +291,44 @@ def bench_greedy(torch, np, api, B, synth, dev, args):
             "closed_form": {"max_order20": 5.0870320785, "min_order20": -5.0870320785}}
 
 
+def bench_anneal(torch, np, api, B, synth, dev, args):
+    """Batched simulated annealing (Methods, "Heuristics") on the 100-variable concatenated PGM
+    within order 20: 1024 chains x 800 iterations, T0 = 0.2, alpha = 0.99, FP64 evaluation of each
+    iteration's 1024 proposals in one call.  The oracle's annealer runs beside it on 64 chains x 30
+    iterations."""
+    from paper_2501_03381_amd import search
+    S = synth.concatenated_100()
+    Sd = torch.from_numpy(S).to(dev)
+    kappa, iters = 1024, 800
+    m0 = synth.sa_initial(31, kappa, 100, 20, 20)
+    dr = synth.sa_draws(32, iters, kappa)
+    res = {}
+    for maximize in (True, False):
+        search.anneal(Sd, m0[:8], {k: v[:2, :8] for k, v in dr.items()}, maximize=maximize)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        best, vb, _, _, acc = search.anneal(Sd, m0, dr, T0=0.2, alpha=0.99, maximize=maximize)
+        dt = time.perf_counter() - t0
+        i = int(np.argmax(vb) if maximize else np.argmin(vb))
+        res["max" if maximize else "min"] = {
+            "seconds": dt, "nplets_evaluated": kappa * (iters + 1), "nplets_per_s": kappa * (iters + 1) / dt,
+            "best_omega": float(vb[i]), "best_solution": [int(x) for x in np.nonzero(best[i])[0]],
+            "chains_at_block": int(np.sum(np.abs(vb - vb[i]) < 1e-9)), "mean_acceptance": float(acc.mean() / iters)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle import search as osearch
+        oracle.build()
+        t0 = time.perf_counter()
+        osearch.anneal(S, m0[:64], {k: v[:30, :64] for k, v in dr.items()}, T0=0.2, alpha=0.99)
+        dt = time.perf_counter() - t0
+        cpu = {"value": 64 * 31 / dt, "unit": "n-plets/s", "cores": oracle.max_threads(0), "kind": "oracle",
+               "sample": f"oracle annealer, 64 chains x 30 iterations, order 20: {64 * 31} n-plets in {dt:.2f} s"}
+    return {"workload": "anneal100: concatenated PGM, order 20, 1024 chains x 800 iterations, FP64",
+            "metric": "n-plets/s", "value": res["max"]["nplets_per_s"], "unit": "n-plets/s", "detail": res,
+            "cpu_baseline": cpu, "closed_form": {"max_order20": 5.0870320785, "min_order20": -5.0870320785}}
+
+
 def bench_grad(torch, np, api, B, synth, dev, args):
     """N=100, T=2000 latent model: 10^5 n-plets of order U{8..20}; forward (Omega, S, TC, DTC) plus
     the adjoint d(sum Omega)/d Sigma."""
@@ -350,7 +388,7 @@ def main():
 
     if args.workload != "latent20":
         extra = {"ar1_30": bench_ar1_30, "uneven1024": bench_uneven, "latent100_grad": bench_grad,
-                 "classes": bench_classes, "greedy100": bench_greedy}[args.workload]
+                 "classes": bench_classes, "greedy100": bench_greedy, "anneal100": bench_anneal}[args.workload]
         print(json.dumps(extra(torch, np, api, B, synth, dev, args)), flush=True)
         return
 

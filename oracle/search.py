@@ -97,3 +97,54 @@ def swap_refine(S, sol, maximize=True, top_m=None, max_iter=50, tol=1e-7):
         cur, val = best[1], best[2]
         it += 1
     return cur, val, it
+
+
+def anneal(S, masks0, draws, T0=1.0, alpha=0.99, maximize=True, mode="within", k_min=3, k_max=None):
+    """Batched simulated annealing over masked n-plets (Methods, "Simulated Annealing Algorithm").
+
+    Every chain proposes one neighbour per iteration: within an order a swap (a member out, an
+    outsider in); across orders an addition when draws['move'] < 1/3, a removal when it is in
+    [1/3, 2/3), else a swap, a swap also replacing a move that would leave [k_min, k_max].  The
+    member and the outsider are the floor(u * count)-th in ascending order, u from draws['a'] and
+    draws['b'].  Energy E = Omega (maximising) or -Omega; a proposal with dE > 0 is taken, otherwise
+    with probability exp(dE / Temp) (the Metropolis rule; the printed rule's sign is garbled),
+    decided by draws['accept'] < exp(dE / Temp).  Temp = T0 * alpha^t.  Non-positive-definite
+    proposals are rejected.
+    """
+    kappa, N = masks0.shape
+    k_max = N - 1 if k_max is None else k_max          # a swap always has an outsider to take in
+    assert k_max <= N - 1 and all(k_min <= m.sum() <= k_max for m in masks0)
+    sign = 1.0 if maximize else -1.0
+    cur = [tuple(int(v) for v in np.nonzero(m)[0]) for m in masks0]
+    E = [sign * o for o in _omega(S, cur)]
+    best, Ebest = list(cur), list(E)
+    accepted = [0] * kappa
+    temp = T0
+    for t in range(draws["accept"].shape[0]):
+        props = []
+        for j in range(kappa):
+            inside = list(cur[j])
+            outside = [v for v in range(N) if v not in cur[j]]
+            k = len(inside)
+            m = draws["move"][t, j]
+            if mode == "across" and m < 1.0 / 3.0 and k < k_max:
+                new = inside + [outside[int(draws["b"][t, j] * len(outside))]]
+            elif mode == "across" and 1.0 / 3.0 <= m < 2.0 / 3.0 and k > k_min:
+                drop = inside[int(draws["a"][t, j] * k)]
+                new = [v for v in inside if v != drop]
+            else:
+                drop = inside[int(draws["a"][t, j] * k)]
+                new = [v for v in inside if v != drop] + [outside[int(draws["b"][t, j] * len(outside))]]
+            props.append(tuple(sorted(new)))
+        Ep = [sign * o for o in _omega(S, props)]
+        for j in range(kappa):
+            if np.isnan(Ep[j]):
+                continue
+            dE = Ep[j] - E[j]
+            if dE > 0 or draws["accept"][t, j] < np.exp(dE / temp):
+                cur[j], E[j] = props[j], Ep[j]
+                accepted[j] += 1
+            if E[j] > Ebest[j]:
+                best[j], Ebest[j] = cur[j], E[j]
+        temp *= alpha
+    return best, [sign * e for e in Ebest], cur, [sign * e for e in E], accepted

@@ -163,3 +163,94 @@ def swap_refine(Sigma: torch.Tensor, solutions: np.ndarray, maximize: bool = Tru
             vals[r] = om[pick]
             iters[r] += 1
     return sols, vals, iters
+
+
+# ------------------------------------------------------------------------------------------------ annealing
+def _propose(cur: np.ndarray, move: np.ndarray, a: np.ndarray, b: np.ndarray, mode: str, k_min: int,
+             k_max: int) -> np.ndarray:
+    """One neighbour per chain.  Within an order: swap a member for an outsider.  Across orders:
+    add (move < 1/3), remove (move in [1/3, 2/3)) or swap, a swap also replacing a move that would
+    leave [k_min, k_max].  The member / outsider is the floor(u * count)-th in ascending order."""
+    kappa, N = cur.shape
+    k = cur.sum(1)
+    if mode == "across":
+        add = (move < 1.0 / 3.0) & (k < k_max)
+        rem = (move >= 1.0 / 3.0) & (move < 2.0 / 3.0) & (k > k_min)
+    else:
+        add = rem = np.zeros(kappa, dtype=bool)
+    swap = ~(add | rem)
+    rows = np.arange(kappa)
+    # the (p+1)-th member / outsider of each row, by running counts
+    pa = (a * k).astype(np.int64)
+    drop = np.argmax(cur & (np.cumsum(cur, 1) == (pa + 1)[:, None]), axis=1)
+    out = ~cur
+    pb = (b * (N - k)).astype(np.int64)
+    take = np.argmax(out & (np.cumsum(out, 1) == (pb + 1)[:, None]), axis=1)
+    prop = cur.copy()
+    d = swap | rem
+    prop[rows[d], drop[d]] = False
+    t = swap | add
+    prop[rows[t], take[t]] = True
+    return prop
+
+
+def _omega_masks(S: torch.Tensor, masks: np.ndarray, precision: str) -> np.ndarray:
+    N = masks.shape[1]
+    odt = torch.float64 if precision == "fp64" else torch.float32
+    if N <= 64:
+        bits = (masks.astype(np.uint64) << np.arange(N, dtype=np.uint64)[None, :]).sum(1, dtype=np.uint64)
+        mt = torch.from_numpy(bits.view(np.int64)).to(S.device)
+        out, _ = api.nplets_measures(S, masks=mt, precision=precision, out_dtype=odt)
+    else:
+        k = int(masks.sum(1).max())
+        rows = -np.ones((len(masks), k), dtype=np.int32)
+        for j, m in enumerate(masks):
+            nz = np.nonzero(m)[0]
+            rows[j, : len(nz)] = nz
+        out, _ = api.nplets_measures(S, nplets=_rows_to_device(rows, S.device), precision=precision, out_dtype=odt)
+    return out[2].double().cpu().numpy().reshape(-1)
+
+
+def anneal(Sigma: torch.Tensor, masks0: np.ndarray, draws: dict, T0: float = 1.0, alpha: float = 0.99,
+           maximize: bool = True, mode: str = "within", k_min: int = 3, k_max: int | None = None,
+           precision: str = "fp64"):
+    """Batched simulated annealing (Methods, "Heuristics", "Simulated Annealing Algorithm").
+
+    kappa chains start from masks0 [kappa][N] (orders may differ: one call evaluates the mixed
+    orders together, MASK selection for N <= 64, else LIST).  Per iteration every chain proposes a
+    neighbour; with energy E = Omega (maximise) or -Omega (minimise) and dE = E_new - E_cur, the
+    proposal is taken if dE > 0, else with probability exp(dE / Temp) (the printed rule has the
+    sign garbled; this is the standard Metropolis reading), decided by draws['accept'].  Temp
+    starts at T0 and is multiplied by alpha each iteration.  Proposals that are not positive
+    definite are rejected.  Returns (best masks, best Omega, final masks, final Omega, accepted
+    count per chain).
+    """
+    if mode not in ("within", "across"):
+        raise ValueError("mode is 'within' or 'across'")
+    S = Sigma[0] if Sigma.dim() == 3 else Sigma
+    cur = np.array(masks0, dtype=bool, copy=True)
+    kappa, N = cur.shape
+    k_max = N - 1 if k_max is None else k_max          # a swap always has an outsider to take in
+    ks = cur.sum(1)
+    if k_max > N - 1 or k_min < 1 or ks.min() < k_min or ks.max() > k_max:
+        raise ValueError("need 1 <= k_min <= every initial order <= k_max <= N - 1")
+    sign = 1.0 if maximize else -1.0
+    om = _omega_masks(S, cur, precision)
+    E = sign * om
+    best, Ebest = cur.copy(), E.copy()
+    accepted = np.zeros(kappa, dtype=np.int64)
+    temp = T0
+    iters = draws["accept"].shape[0]
+    for t in range(iters):
+        prop = _propose(cur, draws["move"][t], draws["a"][t], draws["b"][t], mode, k_min, k_max)
+        Ep = sign * _omega_masks(S, prop, precision)
+        dE = Ep - E
+        with np.errstate(over="ignore", invalid="ignore"):
+            take = (dE > 0) | (draws["accept"][t] < np.exp(dE / temp))
+        take &= ~np.isnan(Ep)
+        cur[take], E[take] = prop[take], Ep[take]
+        accepted += take
+        better = E > Ebest
+        best[better], Ebest[better] = cur[better], E[better]
+        temp *= alpha
+    return best, sign * Ebest, cur, sign * E, accepted

@@ -157,3 +157,23 @@ def random_nplets(rng: np.random.Generator, N: int, B: int, k_lo: int, k_hi: int
     for b in range(B):
         idx[b, : ks[b]] = np.sort(rng.choice(N, size=int(ks[b]), replace=False))
     return idx
+
+
+# --------------------------------------------------------------------------- search inputs
+def sa_initial(seed: int, kappa: int, N: int, k_lo: int, k_hi: int) -> np.ndarray:
+    """kappa random n-plets as boolean masks [kappa][N]: order ~ U{k_lo..k_hi}, members uniform
+    without replacement."""
+    rng = np.random.default_rng(seed)
+    masks = np.zeros((kappa, N), dtype=bool)
+    for j in range(kappa):
+        k = int(rng.integers(k_lo, k_hi + 1))
+        masks[j, rng.choice(N, size=k, replace=False)] = True
+    return masks
+
+
+def sa_draws(seed: int, iters: int, kappa: int) -> dict:
+    """Uniform [0, 1) draws consumed by the annealing searches: per (iteration, chain) one for the
+    move type, one to pick a member, one to pick an outsider and one for acceptance."""
+    rng = np.random.default_rng(seed)
+    u = rng.random((4, iters, kappa))
+    return {"move": u[0], "a": u[1], "b": u[2], "accept": u[3]}

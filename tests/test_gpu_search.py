@@ -130,3 +130,34 @@ def test_swap_refine_pgm_and_ranked(env):
     assert np.all(vals <= v0 + 1e-12)
     check = orc.eval_list(Sl, orc.pad_list([tuple(r) for r in sols]))[0][2]
     assert np.abs(check - vals).max() < 1e-9
+
+
+@pytest.mark.parametrize("mode", ["within", "across"])
+def test_anneal_matches_oracle(env, mode):
+    torch, search, osearch, synth, orc = env
+    S = orc.gc_covariance(synth.latent_20())
+    m0 = synth.sa_initial(21, 48, 20, 3, 10)           # mixed orders in every batch
+    dr = synth.sa_draws(22, 60, 48)
+    for maximize in (True, False):
+        say(f"anneal latent_20 kappa 48 x 60 iterations mode={mode} maximize={maximize} fp64")
+        best, vb, cur, vc, acc = search.anneal(dev(torch, S), m0, dr, T0=0.05, alpha=0.95, maximize=maximize,
+                                               mode=mode)
+        rb, rvb, rc, rvc, racc = osearch.anneal(S, m0, dr, T0=0.05, alpha=0.95, maximize=maximize, mode=mode)
+        assert [tuple(np.nonzero(m)[0]) for m in best] == list(rb)
+        assert [tuple(np.nonzero(m)[0]) for m in cur] == list(rc)
+        assert list(acc) == list(racc)
+        assert np.abs(vb - np.array(rvb)).max() < 1e-9 and np.abs(vc - np.array(rvc)).max() < 1e-9
+
+
+def test_anneal_pgm_blocks(env):
+    torch, search, osearch, synth, orc = env
+    S = synth.block_diag(synth.r_system(5, 1.0), synth.s_system(5, 1.0), np.eye(6))
+    m0 = synth.sa_initial(11, 32, 18, 3, 8)
+    dr = synth.sa_draws(12, 300, 32)
+    say("anneal small PGM across orders, maximise and minimise")
+    best, vb, _, _, _ = search.anneal(dev(torch, S), m0, dr, T0=0.5, alpha=0.98, maximize=True, mode="across")
+    i = int(np.argmax(vb))
+    assert abs(vb[i] - omega_r_block(6, 1.0)) < 1e-9 and best[i][:6].all()
+    best, vb, _, _, _ = search.anneal(dev(torch, S), m0, dr, T0=0.5, alpha=0.98, maximize=False, mode="across")
+    i = int(np.argmin(vb))
+    assert abs(vb[i] + omega_r_block(6, 1.0)) < 1e-9 and best[i][6:12].all()

@@ -115,3 +115,36 @@ def test_swap_refine_ranked_is_monotone_and_locally_optimal(osearch, orc):
                     for u in sol for v in range(14) if v not in sol)[:8]
     nb = [tuple(sorted([x for x in sol if x != u] + [v])) for _, u, v in ranked]
     assert np.nanmin(osearch._omega(S, nb)) >= val - 1e-7
+
+
+# ------------------------------------------------------------------------------------------------ annealing
+def small_pgm():
+    """R-system (5 inputs, c=1) | S-system (5 inputs, c=1) | 6 independent: N = 18."""
+    return synth.block_diag(synth.r_system(5, 1.0), synth.s_system(5, 1.0), np.eye(6))
+
+
+def test_anneal_across_orders_finds_the_blocks(osearch):
+    S = small_pgm()
+    m0 = synth.sa_initial(11, 32, 18, 3, 8)
+    dr = synth.sa_draws(12, 300, 32)
+    best, vb, _, _, _ = osearch.anneal(S, m0, dr, T0=0.5, alpha=0.98, maximize=True, mode="across")
+    i = int(np.argmax(vb))
+    assert abs(vb[i] - omega_r_block(6, 1.0)) < 1e-9 and set(range(6)) <= set(best[i])
+    best, vb, _, _, _ = osearch.anneal(S, m0, dr, T0=0.5, alpha=0.98, maximize=False, mode="across")
+    i = int(np.argmin(vb))
+    assert abs(vb[i] + omega_r_block(6, 1.0)) < 1e-9 and set(range(6, 12)) <= set(best[i])
+
+
+def test_anneal_temperature_limits(osearch):
+    S = synth.random_spd(np.random.default_rng(13), 12, 20.0)
+    m0 = synth.sa_initial(14, 16, 12, 3, 6)
+    dr = synth.sa_draws(15, 40, 16)
+    # infinite temperature: every (positive-definite) proposal is taken
+    _, _, _, _, acc = osearch.anneal(S, m0, dr, T0=1e300, alpha=1.0, mode="across")
+    assert all(a == 40 for a in acc)
+    # zero temperature: only non-worsening moves, so the final energy is the best one and no worse
+    # than the start
+    e0 = osearch._omega(S, [tuple(np.nonzero(m)[0]) for m in m0])
+    best, vb, cur, vc, _ = osearch.anneal(S, m0, dr, T0=1e-300, alpha=1.0, maximize=True, mode="within")
+    assert np.all(np.array(vc) >= e0 - 1e-15) and np.allclose(vc, vb, rtol=0, atol=0)
+    assert [len(c) for c in cur] == [int(m.sum()) for m in m0]          # within: orders kept
