@@ -68,7 +68,8 @@ def parse():
     p.add_argument("--skip-fp64", action="store_true")
     p.add_argument("--no-saturated", action="store_true", help="skip the 64-replica saturation run")
     p.add_argument("--workload", default="latent20",
-                   choices=["latent20", "ar1_30", "uneven1024", "latent100_grad", "classes", "greedy100", "anneal100"],
+                   choices=["latent20", "ar1_30", "uneven1024", "latent100_grad", "classes", "greedy100", "anneal100",
+                            "paired64"],
                    help="latent20: the headline N=20 step (default); the others time the remaining "
                         "configurations of the method (one JSON line each)")
     p.add_argument("--profile-kernels", action="store_true",
@@ -329,6 +330,57 @@ def bench_anneal(torch, np, api, B, synth, dev, args):
             "cpu_baseline": cpu, "closed_form": {"max_order20": 5.0870320785, "min_order20": -5.0870320785}}
 
 
+def bench_paired(torch, np, api, B, synth, dev, args):
+    """Objectives over datasets: 32 subjects x 2 conditions (64 datasets, N=20, T=2000, a
+    synergistic triplet planted in condition A).  Copula + covariance of all 64 datasets in one
+    call each, every n-plet of orders 3..6 evaluated against all 64 covariance matrices (the
+    paper's B x D pairing), then the paired effect size of Omega per n-plet with a top-16 /
+    bottom-16 reduction; then the multi-dataset greedy (orders 3..10, kappa 16)."""
+    from paper_2501_03381_amd import search
+    X = torch.from_numpy(synth.condition_pairs(32, N=20, T=2000)).to(dev)
+    D, T, N = X.shape
+    Sig = api.gc_covariance(X)
+    sel = api.range_selection(N, 3, 6)
+    ev = api.Evaluator(D, N, sel, api.make_opts("fp32_refine"), dev)
+    Bn = ev.nout
+
+    def step(st):
+        ev(Sig, stream=st.value)
+
+    t_eval = kernel_ms(torch, step, reps=10)
+    out, _ = ev(Sig)
+    t0 = time.perf_counter()
+    obj, red = api.objective(out[2], "paired_effect", topk=16)
+    torch.cuda.synchronize()
+    t_obj = (time.perf_counter() - t0) * 1e3
+    tv, tg, _ = red.result()
+    best = api.unrank(N, 3, int(tg[0, 0, 1, 0]))
+    t0 = time.perf_counter()
+    g = search.greedy_multi(Sig, 3, 10, kappa=16, kind="paired_effect", maximize=False, precision="fp32_refine")
+    torch.cuda.synchronize()
+    t_greedy = time.perf_counter() - t0
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        Sh = Sig.cpu().numpy()
+        idx = oracle.enumerate_nplets(N, 3, 3)
+        t0 = time.perf_counter()
+        vals = np.stack([oracle.eval_list(Sh[d], idx)[0][2] for d in range(D)])
+        ref = oracle.objective(vals, "paired_effect")
+        dt = time.perf_counter() - t0
+        cpu = {"value": D * len(idx) / dt, "unit": "n-plet x dataset evaluations/s", "cores": oracle.max_threads(0),
+               "kind": "oracle", "sample": f"all {len(idx)} triplets x {D} datasets + paired effect, {dt:.2f} s",
+               "best_triplet": [int(x) for x in idx[int(np.nanargmin(ref))] if x >= 0]}
+    return {"workload": "paired64: 32 subjects x 2 conditions, N=20, T=2000, planted synergistic triplet (2, 5, 9); "
+                        "orders 3..6 against 64 covariance matrices, paired effect size of Omega",
+            "metric": "n-plet x dataset evaluations/s", "value": D * Bn / (t_eval * 1e-3),
+            "unit": "evaluations/s", "nplets": Bn, "datasets": D, "eval_ms": t_eval, "objective_ms": t_obj,
+            "most_negative_effect": float(tv[0, 0, 1, 0]), "best_nplet": list(best),
+            "greedy_seconds": t_greedy, "greedy_best": {k: [int(x) for x in g[k][0][0]] for k in (3, 6, 10)},
+            "cpu_baseline": cpu}
+
+
 def bench_grad(torch, np, api, B, synth, dev, args):
     """N=100, T=2000 latent model: 10^5 n-plets of order U{8..20}; forward (Omega, S, TC, DTC) plus
     the adjoint d(sum Omega)/d Sigma."""
@@ -388,7 +440,8 @@ def main():
 
     if args.workload != "latent20":
         extra = {"ar1_30": bench_ar1_30, "uneven1024": bench_uneven, "latent100_grad": bench_grad,
-                 "classes": bench_classes, "greedy100": bench_greedy, "anneal100": bench_anneal}[args.workload]
+                 "classes": bench_classes, "greedy100": bench_greedy, "anneal100": bench_anneal,
+                 "paired64": bench_paired}[args.workload]
         print(json.dumps(extra(torch, np, api, B, synth, dev, args)), flush=True)
         return
 

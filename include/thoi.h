@@ -210,6 +210,30 @@ thoi_status thoi_multi_offsets(const int32_t* N_d, int64_t D, int32_t kmin, int3
 size_t thoi_multi_workspace_bytes(const int32_t* N_d, int64_t D, int32_t kmin, int32_t kmax,
                                   const thoi_eval_opts* opts);
 
+/*
+ * Objectives over datasets (Discussion: functions of the measures, such as effect sizes,
+ * optimised across datasets; Methods, "Greedy Algorithm": a function over a sequence of
+ * datasets).  One FP64 value per n-plet b from its values v[d][b] in D datasets:
+ *   THOI_OBJ_MEAN           mean over d = 0..D-1 (summed in ascending d).
+ *   THOI_OBJ_PAIRED_EFFECT  D = 2P datasets, dataset p paired with P + p: x_p = v[p][b] - v[P+p][b],
+ *                           objective = mean(x) / sd(x) with sd on P - 1 degrees of freedom
+ *                           (P >= 2); NaN when sd = 0.
+ * A NaN among the inputs gives NaN.
+ *   vals: device [D][B], val_dtype THOI_DTYPE_F64 or F32 (e.g. one plane of thoi_nplets_eval's out,
+ *         which is [P][D][B]: pass out + m*D*B for measure m).
+ *   obj:  device [B] FP64, or NULL.
+ *   red:  NULL, or a reducer with kmax = 0 (one list: top_val/top_g [1][1][2][topk], hist
+ *         [1][1][hist_bins+2], hist_lo_hi host [1][2]); it receives (objective, b) with ties
+ *         ordered by the lower b, NaN objectives not counted, and is merged into across calls
+ *         (initialise it with thoi_reduce_init(red, 1, 0, stream)).
+ *   ws:   device, >= thoi_objective_workspace_bytes(D, B, red).
+ * Needs obj or red.  D <= 65535 (PAIRED_EFFECT: even D >= 4), B <= 2^40.
+ */
+enum { THOI_OBJ_MEAN = 0, THOI_OBJ_PAIRED_EFFECT = 1 };
+thoi_status thoi_objective(const void* vals, int32_t val_dtype, int64_t D, int64_t B, int32_t kind, double* obj,
+                           const thoi_reduce* red, void* ws, size_t ws_bytes, void* stream);
+size_t thoi_objective_workspace_bytes(int64_t D, int64_t B, const thoi_reduce* red);
+
 /* Initialise reducer arrays for D datasets (top_g = -1, hist = 0). */
 thoi_status thoi_reduce_init(const thoi_reduce* red, int64_t D, int32_t kmax, void* stream);
 

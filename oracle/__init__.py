@@ -241,3 +241,18 @@ def histogram(values: np.ndarray, lo: float, hi: float, bins: int) -> np.ndarray
     out[bins] = int(under.sum())
     out[bins + 1] = int(over.sum())
     return out
+
+
+def objective(vals: np.ndarray, kind: str) -> np.ndarray:
+    """One value per column of vals [D][B]: "mean" over the D rows, or "paired_effect" for D = 2P:
+    x_p = vals[p] - vals[P + p], mean(x) / sd(x) with sd on P - 1 degrees of freedom (NaN when
+    sd = 0).  NaN inputs give NaN."""
+    v = np.asarray(vals, dtype=np.float64)
+    if kind == "mean":
+        return v.mean(axis=0)
+    P = v.shape[0] // 2
+    x = v[:P] - v[P:]
+    m = x.mean(axis=0)
+    sd = np.sqrt(((x - m) ** 2).sum(axis=0) / (P - 1))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.where(sd > 0, m / sd, np.nan)

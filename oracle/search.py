@@ -148,3 +148,25 @@ def anneal(S, masks0, draws, T0=1.0, alpha=0.99, maximize=True, mode="within", k
                 best[j], Ebest[j] = cur[j], E[j]
         temp *= alpha
     return best, [sign * e for e in Ebest], cur, [sign * e for e in E], accepted
+
+
+def greedy_multi(Sigmas, k_first, k_last, kappa=16, measure="omega", kind="mean", maximize=True):
+    """Greedy growth on an objective over datasets: each candidate's measure in every covariance
+    matrix, combined by oracle.objective, the kappa best kept (ties: lexicographic)."""
+    from . import objective
+    m = {"tc": 0, "dtc": 1, "omega": 2, "s": 3}[measure]
+    D, N, _ = Sigmas.shape
+
+    def score(tuples):
+        idx = pad_list(tuples, max(len(t) for t in tuples))
+        vals = np.stack([eval_list(Sigmas[d], idx)[0][m] for d in range(D)])
+        return objective(vals, kind)
+
+    first = [tuple(int(x) for x in row if x >= 0) for row in enumerate_nplets(N, k_first, k_first)]
+    sols, vals = _select(first, score(first), kappa, maximize)
+    out = {k_first: (sols, vals)}
+    for k in range(k_first + 1, k_last + 1):
+        cand = sorted({tuple(sorted(s + (v,))) for s in sols for v in range(N) if v not in s})
+        sols, vals = _select(cand, score(cand), kappa, maximize)
+        out[k] = (sols, vals)
+    return out

@@ -324,6 +324,34 @@ def nplets_reduce(Sigma: torch.Tensor, *, orders=None, g_range=None, nplets=None
     return state
 
 
+# ------------------------------------------------------------------------------------------------ objectives over datasets
+OBJECTIVES = {"mean": B.THOI_OBJ_MEAN, "paired_effect": B.THOI_OBJ_PAIRED_EFFECT}
+
+
+def objective(vals: torch.Tensor, kind: str = "mean", *, write: bool = True, topk: int = 0, hist_bins: int = 0,
+              hist_range=(-10.0, 10.0), state: ReduceState | None = None):
+    """One value per n-plet from its values in D datasets (thoi_objective).
+
+    vals: [D, B] float64 or float32 on the device (e.g. one plane of nplets_measures' output).
+    kind: "mean" or "paired_effect" (datasets p and D/2 + p paired).
+    Returns (obj [B] float64 or None, ReduceState or None); topk / hist_bins > 0 (or state=) streams
+    the objective into a one-list reducer (kmax = 0) that merges across calls.
+    """
+    _require_device(vals, "vals")
+    v = vals.contiguous()
+    if v.dim() != 2 or v.dtype not in (torch.float64, torch.float32):
+        raise TypeError("vals must be a [D, B] float64 or float32 tensor")
+    D, Bn = v.shape
+    dt = B.THOI_DTYPE_F64 if v.dtype == torch.float64 else B.THOI_DTYPE_F32
+    obj = torch.empty(Bn, dtype=torch.float64, device=v.device) if write else None
+    if state is None and (topk > 0 or hist_bins > 0):
+        state = ReduceState(1, 0, topk, hist_bins, hist_range, v.device)
+    red = state.struct if state is not None else None
+    ws = _workspace(B.thoi_objective_workspace_bytes(D, Bn, red), v.device)
+    B.thoi_objective(_ptr(v), dt, D, Bn, OBJECTIVES[kind], _ptr(obj), red, _ptr(ws), ws.numel(), _stream(v.device))
+    return obj, state
+
+
 # ------------------------------------------------------------------------------------------------ differentiation
 def _selection(N, orders, g_range, nplets, masks):
     if (orders is not None) + (nplets is not None) + (masks is not None) != 1:

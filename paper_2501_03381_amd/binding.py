@@ -24,6 +24,7 @@ THOI_DTYPE_F64, THOI_DTYPE_F32 = 0, 1
 THOI_SEL_RANGE, THOI_SEL_LIST, THOI_SEL_MASK = 0, 1, 2
 THOI_NPLET_REFINED, THOI_NPLET_NOT_PD = 1, 2
 THOI_WS_COPULIZE, THOI_WS_COV, THOI_WS_EVAL, THOI_WS_BACKWARD = 0, 1, 2, 3
+THOI_OBJ_MEAN, THOI_OBJ_PAIRED_EFFECT = 0, 1
 THOI_MAX_N_RANGE = 62
 THOI_MAX_N = 128
 THOI_MAX_K = 64
@@ -32,7 +33,7 @@ EXPORTS = [
     "thoi_copulize", "thoi_cov", "thoi_nplets_eval", "thoi_nplets_eval_backward", "thoi_reduce_init",
     "thoi_workspace_bytes", "thoi_ws_status_offset", "thoi_count", "thoi_unrank_host", "thoi_bias_offsets",
     "thoi_status_string", "thoi_version", "thoi_nplets_eval_multi", "thoi_multi_offsets",
-    "thoi_multi_workspace_bytes",
+    "thoi_multi_workspace_bytes", "thoi_objective", "thoi_objective_workspace_bytes",
 ]
 
 
@@ -114,10 +115,14 @@ def lib():
     L.thoi_multi_offsets.argtypes = [P, I64, I32, I32, P]
     L.thoi_multi_workspace_bytes.argtypes = [P, I64, I32, I32, OP]
     L.thoi_multi_workspace_bytes.restype = SZ
+    L.thoi_objective.argtypes = [P, I32, I64, I64, I32, P, ctypes.POINTER(ThoiReduce), P, SZ, P]
+    L.thoi_objective_workspace_bytes.argtypes = [I64, I64, ctypes.POINTER(ThoiReduce)]
+    L.thoi_objective_workspace_bytes.restype = SZ
     L.thoi_version.argtypes = []
     L.thoi_version.restype = ctypes.c_char_p
     for fn in ("thoi_copulize", "thoi_cov", "thoi_nplets_eval", "thoi_nplets_eval_backward", "thoi_reduce_init",
-               "thoi_unrank_host", "thoi_bias_offsets", "thoi_nplets_eval_multi", "thoi_multi_offsets"):
+               "thoi_unrank_host", "thoi_bias_offsets", "thoi_nplets_eval_multi", "thoi_multi_offsets",
+               "thoi_objective"):
         getattr(L, fn).restype = I32
     _lib = L
     return L
@@ -170,6 +175,16 @@ def thoi_multi_offsets(N_d, kmin: int, kmax: int):
 
 def thoi_multi_workspace_bytes(N_d, D, kmin, kmax, opts: ThoiEvalOpts) -> int:
     return int(lib().thoi_multi_workspace_bytes(N_d, D, kmin, kmax, ctypes.byref(opts)))
+
+
+def thoi_objective(vals, val_dtype, D, B, kind, obj, red, ws, ws_bytes, stream):
+    check("thoi_objective", lib().thoi_objective(vals, val_dtype, D, B, kind, obj,
+                                                 ctypes.byref(red) if red is not None else None, ws, ws_bytes,
+                                                 stream))
+
+
+def thoi_objective_workspace_bytes(D, B, red=None) -> int:
+    return int(lib().thoi_objective_workspace_bytes(D, B, ctypes.byref(red) if red is not None else None))
 
 
 def thoi_workspace_bytes(which, D, T, N, sel=None, opts=None) -> int:

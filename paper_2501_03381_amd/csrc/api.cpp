@@ -7,6 +7,8 @@
 
 #include "thoi_internal.hpp"
 
+#include <cmath>
+
 namespace thoi {
 
 thoi_status hip_status(hipError_t e) { return e == hipSuccess ? THOI_OK : THOI_EHIP; }
@@ -314,6 +316,34 @@ thoi_status thoi_reduce_init(const thoi_reduce* red, int64_t D, int32_t kmax, vo
     if (D > 0 && red->topk > 0 && (!red->top_val || !red->top_g)) return THOI_EINVAL;
     if (D > 0 && red->hist_bins > 0 && !red->hist) return THOI_EINVAL;
     return launch_reduce_init(red, D, kmax, (hipStream_t)stream);
+}
+
+thoi_status thoi_objective(const void* vals, int32_t val_dtype, int64_t D, int64_t B, int32_t kind, double* obj,
+                           const thoi_reduce* red, void* ws, size_t ws_bytes, void* stream)
+{
+    if (D < 1 || B < 0 || !valid_dtype(val_dtype)) return THOI_EINVAL;
+    if (kind != THOI_OBJ_MEAN && kind != THOI_OBJ_PAIRED_EFFECT) return THOI_EINVAL;
+    if (kind == THOI_OBJ_PAIRED_EFFECT && (D % 2 != 0 || D < 4)) return THOI_EINVAL;
+    if (!obj && !red) return THOI_EINVAL;
+    if (D > 65535 || B > ((int64_t)1 << 40)) return THOI_EUNSUPPORTED;
+    if (B > 0 && !vals) return THOI_EINVAL;
+    if (red) {
+        if (red->topk < 0 || red->hist_bins < 0 || (red->topk == 0 && red->hist_bins == 0)) return THOI_EINVAL;
+        if (red->topk > 256 || red->hist_bins > 4096) return THOI_EUNSUPPORTED;
+        if (red->topk > 0 && (!red->top_val || !red->top_g)) return THOI_EINVAL;
+        if (red->hist_bins > 0) {
+            if (!red->hist || !red->hist_lo_hi) return THOI_EINVAL;
+            const double lo = red->hist_lo_hi[0], hi = red->hist_lo_hi[1];
+            if (!(lo < hi) || !std::isfinite(lo) || !std::isfinite(hi)) return THOI_EINVAL;
+        }
+    }
+    if (!ws || ws_bytes < objective_ws_bytes(D, B, red)) return THOI_EWORKSPACE;
+    return launch_objective(vals, val_dtype, D, B, kind, obj, red, ws, (hipStream_t)stream);
+}
+
+size_t thoi_objective_workspace_bytes(int64_t D, int64_t B, const thoi_reduce* red)
+{
+    return (D >= 1 && B >= 0) ? objective_ws_bytes(D, B, red) : 0;
 }
 
 size_t thoi_workspace_bytes(int32_t which, int64_t D, int64_t T, int32_t N, const thoi_nplets* sel,

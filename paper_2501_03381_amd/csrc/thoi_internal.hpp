@@ -84,5 +84,8 @@ thoi_status launch_multi(const double* Sigma, const int32_t* N_d, const int32_t*
 size_t multi_ws_bytes(const int32_t* N_d, int64_t D, int32_t kmin, int32_t kmax, const thoi_eval_opts* opts);
 size_t multi_lds_bytes(int32_t nmax, int32_t kmax, const thoi_eval_opts* opts);
 int multi_lane_max(int32_t precision);
+thoi_status launch_objective(const void* vals, int32_t val_dtype, int64_t D, int64_t B, int32_t kind, double* obj,
+                             const thoi_reduce* red, void* ws, hipStream_t s);
+size_t objective_ws_bytes(int64_t D, int64_t B, const thoi_reduce* red);
 
 }  // namespace thoi

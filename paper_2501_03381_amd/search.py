@@ -254,3 +254,37 @@ def anneal(Sigma: torch.Tensor, masks0: np.ndarray, draws: dict, T0: float = 1.0
         best[better], Ebest[better] = cur[better], E[better]
         temp *= alpha
     return best, sign * Ebest, cur, sign * E, accepted
+
+
+# ------------------------------------------------------------------------------------------------ across datasets
+MEASURES = {"tc": 0, "dtc": 1, "omega": 2, "s": 3}
+
+
+def _best_rows_multi(Sigmas: torch.Tensor, rows: np.ndarray, kappa: int, measure: str, kind: str, maximize: bool,
+                     precision: str):
+    odt = torch.float64 if precision == "fp64" else torch.float32
+    out, _ = api.nplets_measures(Sigmas, nplets=_rows_to_device(rows, Sigmas.device), precision=precision,
+                                 out_dtype=odt)
+    _, st = api.objective(out[MEASURES[measure]], kind, write=False, topk=kappa)
+    tv, tg, _ = st.result()
+    slot = 0 if maximize else 1
+    g = tg[0, 0, slot]
+    keep = g >= 0
+    return rows[g[keep]], tv[0, 0, slot][keep]
+
+
+def greedy_multi(Sigmas: torch.Tensor, k_first: int, k_last: int, kappa: int = 16, measure: str = "omega",
+                 kind: str = "mean", maximize: bool = True, precision: str = "fp64"):
+    """Greedy growth (as `greedy`) on an objective over D datasets: every candidate is evaluated in
+    all D covariance matrices in one call (the paper's B x D pairing), `kind` ("mean" or
+    "paired_effect") turns its D values of `measure` into one number on the device, and the kappa
+    best are kept by the reducer.  Sigmas: [D, N, N] float64.  Returns {k: (solutions, objective)}."""
+    import itertools
+    D, N, _ = Sigmas.shape
+    rows = np.array(list(itertools.combinations(range(N), k_first)), dtype=np.int32).reshape(-1, k_first)
+    sols, vals = _best_rows_multi(Sigmas, rows, kappa, measure, kind, maximize, precision)
+    out = {k_first: (sols, vals)}
+    for k in range(k_first + 1, k_last + 1):
+        sols, vals = _best_rows_multi(Sigmas, expand(sols, N), kappa, measure, kind, maximize, precision)
+        out[k] = (sols, vals)
+    return out

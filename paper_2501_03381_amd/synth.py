@@ -177,3 +177,21 @@ def sa_draws(seed: int, iters: int, kappa: int) -> dict:
     rng = np.random.default_rng(seed)
     u = rng.random((4, iters, kappa))
     return {"move": u[0], "a": u[1], "b": u[2], "accept": u[3]}
+
+
+def condition_pairs(P: int, seed: int = 7, N: int = 12, T: int = 1500, planted=(2, 5, 9)) -> np.ndarray:
+    """P subjects x 2 conditions, stacked [2P][T][N] (condition A for rows 0..P-1, B for P..2P-1,
+    subject p in rows p and P + p).  Every dataset is 2-factor data with subject-specific loadings
+    U(-1, 1) and unit noise; in condition A the planted triplet (i, j, k) has x_k = x_i + x_j +
+    0.5 eps (synergy), in condition B x_k is replaced by independent noise of the same variance."""
+    rng = np.random.default_rng(seed)
+    i, j, k = planted
+    out = np.empty((2 * P, T, N))
+    for p in range(P):
+        L = rng.uniform(-1.0, 1.0, (N, 2))
+        for c in range(2):
+            X = rng.standard_normal((T, 2)) @ L.T + rng.standard_normal((T, N))
+            syn = X[:, i] + X[:, j] + 0.5 * rng.standard_normal(T)
+            X[:, k] = syn if c == 0 else rng.standard_normal(T) * syn.std()
+            out[c * P + p] = X
+    return out

@@ -182,3 +182,22 @@ def test_multi_offsets_and_argument_errors(B):
     assert call(bad.ctypes.data_as(ctypes.c_void_p), 2, 3, 5, opts) == B.THOI_EUNSUPPORTED
     assert call(Np, 5, 3, 5, opts, out=None) == B.THOI_EINVAL
     assert call(Np, 5, 3, 5, B.ThoiEvalOpts(precision=1, out_dtype=1, seg_tiles=-1)) == B.THOI_EINVAL
+
+
+def test_objective_argument_errors(B):
+    L = B.lib()
+    fake = ctypes.c_void_p(0x1000)
+    red = B.ThoiReduce(topk=8, hist_bins=0, top_val=fake, top_g=fake)
+    call = lambda D, Bn, kind, obj=fake, r=None, ws=1 << 20, dt=B.THOI_DTYPE_F64: L.thoi_objective(
+        fake, dt, D, Bn, kind, obj, ctypes.byref(r) if r is not None else None, fake, ws, None)
+    assert call(4, 10, 7) == B.THOI_EINVAL                               # unknown kind
+    assert call(5, 10, B.THOI_OBJ_PAIRED_EFFECT) == B.THOI_EINVAL        # odd D
+    assert call(2, 10, B.THOI_OBJ_PAIRED_EFFECT) == B.THOI_EINVAL        # one pair has no sd
+    assert call(4, 10, B.THOI_OBJ_MEAN, obj=None) == B.THOI_EINVAL       # nothing to produce
+    assert call(0, 10, B.THOI_OBJ_MEAN) == B.THOI_EINVAL
+    assert call(4, 10, B.THOI_OBJ_MEAN, dt=4) == B.THOI_EINVAL
+    assert call(70000, 10, B.THOI_OBJ_MEAN) == B.THOI_EUNSUPPORTED
+    assert call(4, 10, B.THOI_OBJ_MEAN, r=B.ThoiReduce(topk=300, top_val=fake, top_g=fake)) == B.THOI_EUNSUPPORTED
+    assert call(4, 100000, B.THOI_OBJ_MEAN, r=red, ws=16) == B.THOI_EWORKSPACE
+    need = B.thoi_objective_workspace_bytes(4, 100000, red)
+    assert need > B.thoi_objective_workspace_bytes(4, 100000, None) >= 256

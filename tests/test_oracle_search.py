@@ -148,3 +148,27 @@ def test_anneal_temperature_limits(osearch):
     best, vb, cur, vc, _ = osearch.anneal(S, m0, dr, T0=1e-300, alpha=1.0, maximize=True, mode="within")
     assert np.all(np.array(vc) >= e0 - 1e-15) and np.allclose(vc, vb, rtol=0, atol=0)
     assert [len(c) for c in cur] == [int(m.sum()) for m in m0]          # within: orders kept
+
+
+# ------------------------------------------------------------------------------------------------ objectives over datasets
+def test_objective_definitions(orc):
+    v = np.array([[1.0, 5.0, 2.0], [2.0, 5.0, np.nan], [3.0, 5.0, 1.0],
+                  [0.0, 1.0, 0.0], [0.0, 1.0, 0.0], [0.0, 1.0, 0.0]])
+    assert np.allclose(orc.objective(v[:3], "mean")[:2], [2.0, 5.0]) and np.isnan(orc.objective(v[:3], "mean")[2])
+    eff = orc.objective(v, "paired_effect")        # P = 3: x = (1, 2, 3) -> 2 / 1; x = (4, 4, 4) -> sd 0
+    assert abs(eff[0] - 2.0) < 1e-15 and np.isnan(eff[1]) and np.isnan(eff[2])
+    # a t statistic written out: x = (1, 4, 6, 9), mean 5, sd sqrt(34/3)
+    w = np.array([[1.0], [4.0], [6.0], [9.0], [0.0], [0.0], [0.0], [0.0]])
+    assert abs(orc.objective(w, "paired_effect")[0] - 5.0 / math.sqrt(34.0 / 3.0)) < 1e-14
+
+
+def test_greedy_multi_finds_the_planted_condition_effect(osearch, orc):
+    X = synth.condition_pairs(6)
+    Sig = np.stack([orc.gc_covariance(x) for x in X])
+    out = osearch.greedy_multi(Sig, 3, 5, kappa=4, kind="paired_effect", maximize=False)
+    assert out[3][0][0] == (2, 5, 9) and out[3][1][0] < -3.0
+    # one dataset and the mean: the same search as the single-dataset greedy
+    one = osearch.greedy_multi(Sig[:1], 3, 6, kappa=5, kind="mean", maximize=True)
+    ref = osearch.greedy(Sig[0], 3, 6, kappa=5, maximize=True)
+    for k in range(3, 7):
+        assert list(one[k][0]) == list(ref[k][0]) and np.allclose(one[k][1], ref[k][1], rtol=0, atol=1e-15)
