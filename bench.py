@@ -74,7 +74,10 @@ def parse():
                         "configurations of the method (one JSON line each)")
     p.add_argument("--profile-kernels", action="store_true",
                    help="only run a 256 MiB device copy 3 times, one step's copula + covariance and the "
-                        "dominant evaluation launch 10 times (for kernel-trace and counter runs), then exit")
+                        "dominant evaluation launch --profile-launches times (for kernel-trace and counter "
+                        "runs), then exit")
+    p.add_argument("--profile-launches", type=int, default=10,
+                   help="dominant launches in --profile-kernels mode (each synchronized)")
     return p.parse_args()
 
 
@@ -453,12 +456,13 @@ def main():
             dst.copy_(src)
         st = Step(torch, B, api, X, "fp32", 9, 12)
         st(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
-        for _ in range(9):
+        for _ in range(max(args.profile_launches, 1) - 1):
             st.evaluate(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
             torch.cuda.synchronize()
         torch.cuda.synchronize()
         print(json.dumps({"profile_kernels": True, "copy_bytes_each_way": src.numel() * 4,
-                          "dominant_nplets": sum(math.comb(N, k) for k in range(9, 13))}), flush=True)
+                          "dominant_nplets": sum(math.comb(N, k) for k in range(9, 13)),
+                          "dominant_launches": max(args.profile_launches, 1)}), flush=True)
         return
 
     # ------------------------------------------------------------------ FP32 + FP64 refinement (the metric)

@@ -392,7 +392,10 @@ Plan make_plan(int N, const thoi_nplets* sel, bool reduce, int precision, int se
     P.wave_tile = reduce ? kWaveTileRed : kWaveTileOut;
     // reduce mode: a workgroup walks a segment of tiles so that one launch has a few thousand
     // workgroups and the number of segments to merge stays bounded
-    P.seg_tiles = 1;
+    // FP64 ranges: two tiles per workgroup amortise the staging of the correlation matrix
+    // (measured faster for FP64; for FP32 the concurrent class launches fill the GPU better with
+    // one tile per workgroup)
+    P.seg_tiles = (sizeof(F) == 8 && sel->mode == THOI_SEL_RANGE) ? 2 : 1;
     if (reduce) {
         const int64_t tiles = (Bn + kTile - 1) / kTile;
         P.seg_tiles = (int)((tiles + 16383) / 16384);
