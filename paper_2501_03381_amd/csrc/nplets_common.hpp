@@ -63,9 +63,11 @@ __device__ constexpr PascalTable kPascal = make_pascal();
 
 // ------------------------------------------------------------------------------------------------
 // Staging of one dataset into LDS: R (precision F), 1/sqrt(Sigma_jj) and log Sigma_jj (FP64).
-// Must be called by the whole block; ends with a barrier.  Every thread loads the entries it
-// writes together with the two variances they are scaled by, in batches of 8 entries whose loads
-// are all in flight at once: the whole staging is one round trip to memory.
+// Must be called by the whole block (after a barrier if the block has used the LDS before); ends
+// with a barrier.  Each thread issues the loads of its first 8 entries together with its diagonal
+// load; N threads compute 1/sqrt(Sigma_jj) and log Sigma_jj once into LDS, and after a barrier
+// every entry is scaled by two of them (entries beyond the first 8 * blockDim are loaded in
+// further batches of 8).
 // ------------------------------------------------------------------------------------------------
 // With sBin, the block also copies C(n, m), n < N, m < kb, into sBin[n * kb + m]; the first
 // entries' loads go out with the correlation loads.
@@ -77,35 +79,42 @@ __device__ __forceinline__ void stage_corr(const double* __restrict__ Sig, int N
     const int NN = N * N;
     const int bd = (int)blockDim.x;
     const int nbin = sBin ? N * kb : 0;
-    const uint64_t b0 = (int)threadIdx.x < nbin ? kPascal.v[threadIdx.x / kb][threadIdx.x % kb] : 0ull;
-    for (int e0 = threadIdx.x; e0 < NN; e0 += 8 * bd) {
-        double v[8], di[8], dj[8];
+    const int tid = (int)threadIdx.x;
+    const uint64_t b0 = tid < nbin ? kPascal.v[tid / kb][tid % kb] : 0ull;
+    // first batch of entries and the diagonal in flight together
+    double v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * bd;
-            const int i = e / N, j = e - i * N;
-            v[u] = e < NN ? Sig[e] : 0.0;
-            di[u] = e < NN ? Sig[(int64_t)i * N + i] : 1.0;
-            dj[u] = e < NN ? Sig[(int64_t)j * N + j] : 1.0;
+    for (int u = 0; u < 8; ++u) {
+        const int e = tid + u * bd;
+        v[u] = e < NN ? Sig[e] : 0.0;
+    }
+    // one reciprocal square root and one log per variable
+    for (int j = tid; j < N; j += bd) {
+        const double dj = Sig[(int64_t)j * N + j];
+        sIsd[j] = dj > 0.0 ? 1.0 / sqrt(dj) : __builtin_nan("");
+        sLogd[j] = log(dj);
+    }
+    if (tid < nbin) sBin[tid] = b0;
+    for (int e = tid + bd; e < nbin; e += bd) sBin[e] = kPascal.v[e / kb][e % kb];
+    __syncthreads();
+    for (int e0 = tid; e0 < NN; e0 += 8 * bd) {
+        if (e0 != tid) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * bd;
+                v[u] = e < NN ? Sig[e] : 0.0;
+            }
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int e = e0 + u * bd;
             if (e < NN) {
                 const int i = e / N, j = e - i * N;
-                const double si = di[u] > 0.0 ? 1.0 / sqrt(di[u]) : __builtin_nan("");
-                const double sj = dj[u] > 0.0 ? 1.0 / sqrt(dj[u]) : __builtin_nan("");
+                const double si = sIsd[i], sj = sIsd[j];
                 sR[e] = (F)((i == j) ? (si == si ? 1.0 : __builtin_nan("")) : v[u] * si * sj);
             }
         }
     }
-    for (int j = threadIdx.x; j < N; j += bd) {
-        const double dj = Sig[(int64_t)j * N + j];
-        sIsd[j] = dj > 0.0 ? 1.0 / sqrt(dj) : __builtin_nan("");
-        sLogd[j] = log(dj);
-    }
-    if ((int)threadIdx.x < nbin) sBin[threadIdx.x] = b0;
-    for (int e = threadIdx.x + bd; e < nbin; e += bd) sBin[e] = kPascal.v[e / kb][e % kb];
     __syncthreads();
 }
 

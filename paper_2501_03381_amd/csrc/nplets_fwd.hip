@@ -536,7 +536,9 @@ void launch_engines(EvalArgs& a, const Plan& P, const RedArgs& red, hipStream_t 
     for (int c = 0; c < ncls; ++c) nl += P.nblk[c] != 0;
     FanScope fan(s, nl);
     int b = 0;
-    for (int c = 0; c < ncls; ++c) {
+    const int* order = sizeof(F) == 4 ? kF32LaunchOrder : kF64LaunchOrder;
+    for (int oc = 0; oc < ncls; ++oc) {
+        const int c = order[oc];
         if (P.nblk[c] == 0) continue;
         const int kb = MODE == THOI_SEL_RANGE ? cls[c].hi : 0;
         const size_t lds = lane_stage_bytes(N, kb, sizeof(F)) + red_lds(reduce);

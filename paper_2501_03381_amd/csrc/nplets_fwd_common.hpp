@@ -19,6 +19,15 @@ constexpr int kListOrders = THOI_MAX_K + 2;   // k = 0..64 and one "invalid" buc
 struct KClass { int lo, hi; };
 constexpr KClass kF32Classes[] = {{0, 8}, {9, 12}, {13, 16}, {17, 20}, {21, 24}};
 constexpr KClass kF64Classes[] = {{0, 6}, {7, 10}, {11, 14}, {15, 18}};
+// Launch order of the classes of one evaluation.  The concurrent class grids start dispatching in
+// launch order, each once the previous one has placed its workgroups.  A class whose grid fits in
+// one round of waves but whose lanes run longest (FP32 orders 13..16 at N = 20) goes first, and
+// the largest grid fills the GPU around it.  FP64 keeps ascending order: its long classes need
+// several rounds at one wave per SIMD and, launched first, hold every SIMD.
+constexpr int kF32LaunchOrder[] = {2, 1, 3, 0, 4};
+constexpr int kF64LaunchOrder[] = {0, 1, 2, 3};
+static_assert(sizeof(kF32LaunchOrder) / sizeof(int) == sizeof(kF32Classes) / sizeof(KClass), "one entry per class");
+static_assert(sizeof(kF64LaunchOrder) / sizeof(int) == sizeof(kF64Classes) / sizeof(KClass), "one entry per class");
 constexpr int kF32LaneMax = 24;
 constexpr int kF64LaneMax = 18;
 
