@@ -207,9 +207,12 @@ __global__ __launch_bounds__(64) void k_refine(EvalArgs a, RangeOrders ro, RedAr
     double* sInv = sM + 64 * ks;
     int* cidx = reinterpret_cast<int*>(sInv + 64);
     __shared__ int sk;
+    // the queue is complete (the class kernels ran before this one); a workgroup without a
+    // queued n-plet leaves before staging anything
+    const uint32_t n = min(a.hdr->refine_count, a.refine_cap);
+    if (blockIdx.x >= n) return;
     if constexpr (MODE == THOI_SEL_RANGE) stage_binomials(N, 64, sBin);
     __syncthreads();
-    const uint32_t n = min(a.hdr->refine_count, a.refine_cap);
     const int lane = threadIdx.x;
     const bool reduce = red.active != 0;
     int staged = -1;

@@ -229,9 +229,12 @@ __global__ __launch_bounds__(64) void k_refine_multi(EvalArgs a, const MultiPlan
     int* cidx = reinterpret_cast<int*>(sInv + 64);
     __shared__ int sk, sd;
     __shared__ int64_t sg;
+    // the queue is complete (the class kernels ran before this one); a workgroup without a
+    // queued n-plet leaves before staging anything
+    const uint32_t n = min(a.hdr->refine_count, a.refine_cap);
+    if (blockIdx.x >= n) return;
     stage_binomials(nmax, 64, sBin);
     __syncthreads();
-    const uint32_t n = min(a.hdr->refine_count, a.refine_cap);
     const int lane = threadIdx.x;
     const bool reduce = red.active != 0;
     int staged = -1;
