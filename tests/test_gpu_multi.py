@@ -109,15 +109,16 @@ def test_tuning_knobs_do_not_change_results(env, tmp_path, monkeypatch):
     from paper_2501_03381_amd import tune
     monkeypatch.setenv("THOI_TUNE_CACHE", str(tmp_path / "tune.json"))
     Sd = api.gc_covariance(dev(torch, synth.latent_20(T=2000)))
-    say("seg_tiles 1 / 3 / 8 give identical RANGE results")
     sel = api.range_selection(20, 3, 20)
-    outs = []
-    for st in (1, 3, 8):
-        ev = api.Evaluator(1, 20, sel, api.make_opts("fp32_refine", seg_tiles=st), Sd.device)
-        o, f = ev(Sd)
-        outs.append((o.clone(), f.clone()))
-    for o, f in outs[1:]:
-        assert torch.equal(o, outs[0][0]) and torch.equal(f, outs[0][1])
+    for prec, odt in (("fp32_refine", torch.float32), ("fp64", torch.float64)):
+        say(f"seg_tiles library choice / 1 / 2 / 3 / 8 give identical RANGE results, {prec}")
+        outs = []
+        for st in (0, 1, 2, 3, 8):
+            ev = api.Evaluator(1, 20, sel, api.make_opts(prec, odt, seg_tiles=st), Sd.device, odt)
+            o, f = ev(Sd)
+            outs.append((o.clone(), f.clone()))
+        for o, f in outs[1:]:
+            assert torch.equal(o, outs[0][0]) and torch.equal(f, outs[0][1])
     say("tune_range")
     r = tune.tune_range(Sd, 3, 20, candidates=(1, 2))
     assert r["seg_tiles"] in (1, 2) and r["ms"] > 0
