@@ -61,6 +61,19 @@ constexpr PascalTable make_pascal()
 }
 __device__ constexpr PascalTable kPascal = make_pascal();
 
+// 1/n for n = 1..63 (entry 0 is 0), correctly rounded at compile time.
+struct RecipTable {
+    double v[64];
+};
+constexpr RecipTable make_recip()
+{
+    RecipTable t{};
+    t.v[0] = 0.0;
+    for (int n = 1; n < 64; ++n) t.v[n] = 1.0 / n;
+    return t;
+}
+__device__ constexpr RecipTable kRecip = make_recip();
+
 // ------------------------------------------------------------------------------------------------
 // Staging of one dataset into LDS: R (precision F), 1/sqrt(Sigma_jj) and log Sigma_jj (FP64).
 // Must be called by the whole block (after a barrier if the block has used the LDS before); ends
@@ -145,29 +158,38 @@ template <int K>
 __device__ __forceinline__ void unrank_lex(uint64_t r, int N, const uint64_t* __restrict__ sBin, int kb,
                                            int (&c)[K > 0 ? K : 1])
 {
-    int x = 0;
     if (N <= 33) {
-        // every C(n, m) with n < 33 fits in 32 bits: walk the low words of the table
-        const uint32_t* b32 = reinterpret_cast<const uint32_t*>(sBin);
-        uint32_t rr = (uint32_t)r;
+        // One pass over the candidate values x = 0..N-1, the same number of steps in every lane.
+        // b = C(N-1-x, m) (m: binomial column of the next free position) is carried in FP64 and
+        // updated by C(n-1, m) = C(n, m) (n-m) / n after a skip and C(n-1, m-1) = C(n, m) m / n
+        // after a take.  With n < 33 every C(n, m) is below 2^32 and every product b * f below
+        // 2^37, so b * f * (1/n) lies within 2^-15 of the integer quotient and rounding recovers it
+        // exactly; the taken values are collected in a bit mask.
+        if constexpr (K >= 1) {
+            double rr = (double)(uint32_t)r;
+            double b = (double)(uint32_t)kPascal.v[N - 1][K - 1];
+            int m = K - 1;
+            uint64_t mask = 0;
+            for (int x = 0; x < N; ++x) {
+                const int n = N - 1 - x;
+                const double inv = kRecip.v[n];
+                const bool take = rr < b;
+                const double bt = rint(b * (double)m * inv);
+                const double bs = rint(b * (double)(n - m) * inv);
+                rr = take ? rr : rr - b;
+                b = take ? bt : bs;
+                m -= take ? 1 : 0;
+                mask |= take ? (1ull << x) : 0ull;
+            }
 #pragma unroll
-        for (int i = 0; i < K; ++i) {
-            const int m = K - 1 - i;
-            if (m == 0) {
-                c[i] = x + (int)rr;
-            } else {
-                while (x < N) {
-                    const uint32_t b = b32[2 * ((N - 1 - x) * kb + m)];
-                    if (rr < b) break;
-                    rr -= b;
-                    ++x;
-                }
-                c[i] = x;
-                ++x;
+            for (int i = 0; i < K; ++i) {
+                c[i] = __builtin_ctzll(mask);
+                mask &= mask - 1;
             }
         }
         return;
     }
+    int x = 0;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const int m = K - 1 - i;
