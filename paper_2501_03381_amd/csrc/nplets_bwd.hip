@@ -164,13 +164,20 @@ __global__ __launch_bounds__(64) void k_backward(BwdArgs a)
             }
         }
         __syncthreads();
-        // G row i, scattered into the accumulator row c_i
+        // U = P diag(1/p) in the rows of sM (W is no longer needed): one reciprocal per column,
+        // then (P diag(1/p) P)_ij = sum_m U_im P_jm (P symmetric; row j is the same for every lane)
+        if (lane < k) sInv[lane] = 1.0 / sP[lane * ks + lane];
+        __syncthreads();
+        if (lane < k) {
+            for (int m = 0; m < k; ++m) sM[lane * ks + m] = sP[lane * ks + m] * sInv[m];
+        }
+        // G row i, scattered into the accumulator row c_i (lane i reads only its own row of U)
         if (lane < k) {
             const int i = lane;
             const int ci = cidx[i];
             for (int j = 0; j < k; ++j) {
                 double q = 0.0;
-                for (int m = 0; m < k; ++m) q += sP[i * ks + m] * sP[m * ks + j] / sP[m * ks + m];
+                for (int m = 0; m < k; ++m) q += sM[i * ks + m] * sP[j * ks + m];
                 const double pij = sP[i * ks + j];
                 const double g = 0.5 * cT * ((i == j ? 1.0 : 0.0) - pij) + 0.5 * cD * (pij - q);
                 const int cj = cidx[j];
