@@ -25,7 +25,10 @@
 namespace thoi {
 namespace {
 
-constexpr int kBwdTile = 128;   // n-plets per workgroup
+constexpr int64_t kBwdTileMin = 16;     // n-plets per workgroup, bounds of the host's choice
+constexpr int64_t kBwdTileMax = 4096;
+constexpr int64_t kLdsPerCu = 160 * 1024;
+constexpr int64_t kCus = 256;
 
 struct BwdArgs {
     const double* Sigma;
@@ -41,6 +44,7 @@ struct BwdArgs {
     int32_t kmax_list;
     const uint64_t* mask;
     int32_t ks;                 // LDS row stride (>= largest order + 1)
+    int64_t tile;               // n-plets per workgroup
 };
 
 // LDS: sIsd [N] f64 | sBin [N*64] u64 (RANGE) | sM [64*ks] f64 | sP [64*ks] f64 | sInv [64] f64 |
@@ -78,8 +82,8 @@ __global__ __launch_bounds__(64) void k_backward(BwdArgs a)
     if constexpr (MODE == THOI_SEL_RANGE) stage_binomials(N, 64, sBin);
     __syncthreads();
 
-    const int64_t b0 = (int64_t)blockIdx.x * kBwdTile;
-    const int64_t b1 = b0 + kBwdTile < a.B ? b0 + kBwdTile : a.B;
+    const int64_t b0 = (int64_t)blockIdx.x * a.tile;
+    const int64_t b1 = b0 + a.tile < a.B ? b0 + a.tile : a.B;
     bool touched = false;
     for (int64_t pos = b0; pos < b1; ++pos) {
         const int64_t o = (int64_t)d * a.B + pos;
@@ -247,7 +251,18 @@ thoi_status launch_backward(const double* Sigma, int64_t D, int32_t N, const tho
     a.ks = (kmax < 64 ? kmax : 64) + 1;
     if (D == 0 || a.B == 0) return THOI_OK;
     const size_t lds = bwd_lds_bytes(N, a.ks, sel->mode == THOI_SEL_RANGE);
-    dim3 grid((unsigned)((a.B + kBwdTile - 1) / kBwdTile), (unsigned)D);
+    // one round of workgroups: as many per dataset as the LDS footprint lets the CUs hold at once
+    // (each workgroup flushes its accumulator tile once, so fewer, longer workgroups also mean
+    // fewer atomics)
+    const int64_t per_cu = (int64_t)(kLdsPerCu / (int64_t)(lds > 0 ? lds : 1));
+    const int64_t resident = kCus * (per_cu > 0 ? per_cu : 1);
+    const int64_t per_d = (resident + D - 1) / D;
+    int64_t tile = (a.B + per_d - 1) / per_d;
+    tile = tile < kBwdTileMin ? kBwdTileMin : (tile > kBwdTileMax ? kBwdTileMax : tile);
+    a.tile = tile;
+    const int64_t nblk = (a.B + tile - 1) / tile;
+    if (nblk > 0x7fffffff) return THOI_EUNSUPPORTED;
+    dim3 grid((unsigned)nblk, (unsigned)D);
     if (sel->mode == THOI_SEL_RANGE) hipLaunchKernelGGL(k_backward<THOI_SEL_RANGE>, grid, dim3(64), lds, s, a);
     else if (sel->mode == THOI_SEL_LIST) hipLaunchKernelGGL(k_backward<THOI_SEL_LIST>, grid, dim3(64), lds, s, a);
     else hipLaunchKernelGGL(k_backward<THOI_SEL_MASK>, grid, dim3(64), lds, s, a);
