@@ -172,6 +172,17 @@ thoi_status thoi_nplets_eval(const double* Sigma, int64_t D, int32_t N, const th
                              void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Host, pure: the launches thoi_nplets_eval would enqueue for the evaluation engines of this
+ * selection on one dataset (the class launches and the large-order engine; not the small
+ * bookkeeping kernels), and the largest number of work-items along x among them.  Every grid is
+ * kept below 2^30 work-items along x (the dispatch limit is 2^32) by giving each workgroup more
+ * n-plets.  Same argument checks as thoi_nplets_eval except those of Sigma and out (no pointer is
+ * dereferenced; LIST and MASK selections still need their non-NULL device pointer).
+ */
+thoi_status thoi_eval_launch_shape(int32_t N, const thoi_nplets* sel, const thoi_eval_opts* opts,
+                                   int32_t* n_launches, int64_t* max_items_x);
+
+/*
  * Adjoint of thoi_nplets_eval: grad_Sigma[d] += sum_b sum_m grad_out[m][d][b] *
  * d measure_m(b, d) / d Sigma_d, with the entries of Sigma treated as
  * independent (the result is symmetric).  FP64 factorisation, FP32 accumulation.

@@ -33,7 +33,7 @@ EXPORTS = [
     "thoi_copulize", "thoi_cov", "thoi_nplets_eval", "thoi_nplets_eval_backward", "thoi_reduce_init",
     "thoi_workspace_bytes", "thoi_ws_status_offset", "thoi_count", "thoi_unrank_host", "thoi_bias_offsets",
     "thoi_status_string", "thoi_version", "thoi_nplets_eval_multi", "thoi_multi_offsets",
-    "thoi_multi_workspace_bytes", "thoi_objective", "thoi_objective_workspace_bytes",
+    "thoi_multi_workspace_bytes", "thoi_objective", "thoi_objective_workspace_bytes", "thoi_eval_launch_shape",
 ]
 
 
@@ -118,11 +118,12 @@ def lib():
     L.thoi_objective.argtypes = [P, I32, I64, I64, I32, P, ctypes.POINTER(ThoiReduce), P, SZ, P]
     L.thoi_objective_workspace_bytes.argtypes = [I64, I64, ctypes.POINTER(ThoiReduce)]
     L.thoi_objective_workspace_bytes.restype = SZ
+    L.thoi_eval_launch_shape.argtypes = [I32, NP, OP, ctypes.POINTER(I32), ctypes.POINTER(I64)]
     L.thoi_version.argtypes = []
     L.thoi_version.restype = ctypes.c_char_p
     for fn in ("thoi_copulize", "thoi_cov", "thoi_nplets_eval", "thoi_nplets_eval_backward", "thoi_reduce_init",
                "thoi_unrank_host", "thoi_bias_offsets", "thoi_nplets_eval_multi", "thoi_multi_offsets",
-               "thoi_objective"):
+               "thoi_objective", "thoi_eval_launch_shape"):
         getattr(L, fn).restype = I32
     _lib = L
     return L
@@ -185,6 +186,14 @@ def thoi_objective(vals, val_dtype, D, B, kind, obj, red, ws, ws_bytes, stream):
 
 def thoi_objective_workspace_bytes(D, B, red=None) -> int:
     return int(lib().thoi_objective_workspace_bytes(D, B, ctypes.byref(red) if red is not None else None))
+
+
+def thoi_eval_launch_shape(N, sel: ThoiNplets, opts: ThoiEvalOpts):
+    """Host: (number of engine launches, largest work-items along x) of thoi_nplets_eval."""
+    n, m = ctypes.c_int32(0), ctypes.c_int64(0)
+    check("thoi_eval_launch_shape", lib().thoi_eval_launch_shape(N, ctypes.byref(sel), ctypes.byref(opts),
+                                                                 ctypes.byref(n), ctypes.byref(m)))
+    return n.value, m.value
 
 
 def thoi_workspace_bytes(which, D, T, N, sel=None, opts=None) -> int:

@@ -221,6 +221,17 @@ thoi_status thoi_nplets_eval(const double* Sigma, int64_t D, int32_t N, const th
     return launch_eval(Sigma, D, N, sel, opts, out, flags, ws, ws_bytes, (hipStream_t)stream);
 }
 
+thoi_status thoi_eval_launch_shape(int32_t N, const thoi_nplets* sel, const thoi_eval_opts* opts,
+                                   int32_t* n_launches, int64_t* max_items_x)
+{
+    if (!n_launches || !max_items_x) return THOI_EINVAL;
+    // D = 0: the same checks as thoi_nplets_eval except those of Sigma and out
+    const thoi_status st = check_eval(nullptr, 0, N, sel, opts, true, nullptr);
+    if (st != THOI_OK) return st;
+    eval_launch_shape(N, sel, opts, n_launches, max_items_x);
+    return THOI_OK;
+}
+
 thoi_status thoi_nplets_eval_backward(const double* Sigma, int64_t D, int32_t N, const thoi_nplets* sel,
                                       const thoi_eval_opts* opts, const float* grad_out, float* grad_Sigma, void* ws,
                                       size_t ws_bytes, void* stream)

@@ -385,6 +385,11 @@ struct Plan {
     int64_t seg_cap;
 };
 
+// Grids are kept well below the dispatch limit of 2^32 work-items along x: a class grid by
+// growing the tiles per workgroup, the wave grid by growing the n-plets per workgroup (both
+// engines loop over their share, so any tile count is valid).
+constexpr int64_t kMaxGridItems = int64_t(1) << 30;
+
 template <typename F>
 Plan make_plan(int N, const thoi_nplets* sel, bool reduce, int precision, int seg_tiles_hint)
 {
@@ -405,6 +410,38 @@ Plan make_plan(int N, const thoi_nplets* sel, bool reduce, int precision, int se
         if (P.seg_tiles < 1) P.seg_tiles = 1;
     }
     if (seg_tiles_hint > 0) P.seg_tiles = seg_tiles_hint;
+    // largest share of one class (or of the wave engine): n-plets per launch bound the grids
+    int64_t cls_cnt[8] = {0}, wave_cnt = 0;
+    if (sel->mode == THOI_SEL_RANGE) {
+        int64_t g = 0;
+        const int64_t gb = sel->g_begin, ge = sel->g_begin + sel->g_count;
+        for (int k = sel->kmin; k <= sel->kmax; ++k) {
+            const int64_t ck = (int64_t)binom_u64(N, k);
+            const int64_t lo = gb > g ? gb : g, hi = ge < g + ck ? ge : g + ck;
+            if (hi > lo) {
+                if (k <= lane_max) cls_cnt[class_of<F>(k)] += hi - lo;
+                else wave_cnt += hi - lo;
+            }
+            g += ck;
+        }
+    } else {
+        for (int c = 0; c < P.ncls; ++c) cls_cnt[c] = Bn;
+        if (sel_kmax(sel, N) > lane_max) wave_cnt = Bn;
+    }
+    for (int c = 0; c < P.ncls; ++c) {
+        // threads of class c at seg_tiles: about cls_cnt / (S * seg_tiles) plus one tile per piece
+        const int S = sel->mode == THOI_SEL_RANGE ? lane_per_thread<F>(cls[c].hi, THOI_SEL_RANGE) : 1;
+        const int64_t threads = cls_cnt[c] / S + (int64_t)kTile * (kMaxPieces + 1);
+        const int64_t need = (threads + kMaxGridItems - 1) / kMaxGridItems;
+        if (need > P.seg_tiles) P.seg_tiles = (int)need;
+    }
+    {
+        const int64_t groups = (wave_cnt + P.wave_tile - 1) / P.wave_tile + kMaxPieces + 1;
+        if (groups * 64 > kMaxGridItems) {
+            const int64_t t = (wave_cnt + kMaxGridItems / 64 - kMaxPieces - 2) / (kMaxGridItems / 64 - kMaxPieces - 1);
+            P.wave_tile = (int)(t > P.wave_tile ? t : P.wave_tile);
+        }
+    }
     const int64_t per_blk = (int64_t)kTile * P.seg_tiles;     // one n-plet per lane (index lists)
     if (sel->mode == THOI_SEL_RANGE) {
         int64_t g = 0;
@@ -718,6 +755,27 @@ thoi_status launch_eval(const double* Sigma, int64_t D, int32_t N, const thoi_np
     if (reduce && red.topk > 0)
         hipLaunchKernelGGL(k_red_final, dim3((unsigned)(kmax + 1), (unsigned)D), dim3(256), 0, s, red, a.hdr);
     return hip_status(hipGetLastError());
+}
+
+void eval_launch_shape(int32_t N, const thoi_nplets* sel, const thoi_eval_opts* opts, int32_t* n_launches,
+                       int64_t* max_items_x)
+{
+    const bool reduce = opts->reduce != nullptr;
+    const Plan P = opts->precision == THOI_FP64 ? make_plan<double>(N, sel, reduce, opts->precision, opts->seg_tiles)
+                                                : make_plan<float>(N, sel, reduce, opts->precision, opts->seg_tiles);
+    int n = 0;
+    int64_t mx = 0;
+    for (int c = 0; c < P.ncls; ++c) {
+        if (P.nblk[c] == 0) continue;
+        ++n;
+        mx = P.nblk[c] * kTile > mx ? P.nblk[c] * kTile : mx;
+    }
+    if (P.wblk) {
+        ++n;
+        mx = P.wblk * 64 > mx ? P.wblk * 64 : mx;
+    }
+    *n_launches = n;
+    *max_items_x = mx;
 }
 
 thoi_status launch_reduce_init(const thoi_reduce* red, int64_t D, int32_t kmax, hipStream_t s)

@@ -72,6 +72,8 @@ thoi_status launch_eval(const double* Sigma, int64_t D, int32_t N, const thoi_np
                         hipStream_t s);
 size_t eval_ws_bytes(int64_t D, int32_t N, const thoi_nplets* sel, const thoi_eval_opts* opts);
 size_t eval_lds_bytes(int32_t N, const thoi_nplets* sel, const thoi_eval_opts* opts);
+void eval_launch_shape(int32_t N, const thoi_nplets* sel, const thoi_eval_opts* opts, int32_t* n_launches,
+                       int64_t* max_items_x);
 thoi_status launch_backward(const double* Sigma, int64_t D, int32_t N, const thoi_nplets* sel,
                             const thoi_eval_opts* opts, const float* grad_out, float* grad_Sigma, void* ws,
                             size_t ws_bytes, hipStream_t s);

@@ -201,3 +201,33 @@ def test_objective_argument_errors(B):
     assert call(4, 100000, B.THOI_OBJ_MEAN, r=red, ws=16) == B.THOI_EWORKSPACE
     need = B.thoi_objective_workspace_bytes(4, 100000, red)
     assert need > B.thoi_objective_workspace_bytes(4, 100000, None) >= 256
+
+
+def test_launch_plan_stays_below_dispatch_limit(B):
+    """Every engine grid stays below 2^30 work-items along x (the dispatch limit is 2^32), also for
+    enumerations whose one-workgroup-per-n-plet wave grid would exceed it: FP64 orders 19..30 at
+    N=30 in output mode (1.08e8 n-plets above the FP64 register classes), full FP32 and FP64
+    enumerations at N = 34..40, and a LIST of 2^33 rows."""
+    lim = 1 << 30
+    fake = ctypes.c_void_p(0x1000)
+    cases = []
+    for prec in (B.THOI_FP64, B.THOI_FP32, B.THOI_FP32_REFINE):
+        cases.append((30, B.ThoiNplets(mode=B.THOI_SEL_RANGE, kmin=19, kmax=30, g_begin=0,
+                                       g_count=B.thoi_count(30, 19, 30)), prec))
+        for N in (34, 40):
+            cases.append((N, B.ThoiNplets(mode=B.THOI_SEL_RANGE, kmin=3, kmax=N, g_begin=0,
+                                          g_count=B.thoi_count(N, 3, N)), prec))
+        cases.append((100, B.ThoiNplets(mode=B.THOI_SEL_LIST, B=1 << 33, kmax_list=40, idx=fake), prec))
+    for N, sel, prec in cases:
+        o = B.ThoiEvalOpts(precision=prec, out_dtype=B.THOI_DTYPE_F32)
+        n, m = B.thoi_eval_launch_shape(N, sel, o)
+        assert 1 <= n <= 6 and 0 < m < lim, (N, prec, n, m)
+    # the N=20 workload keeps its usual shape: one launch per FP32 class, no large-order engine
+    sel = B.ThoiNplets(mode=B.THOI_SEL_RANGE, kmin=3, kmax=20, g_begin=0, g_count=1048365)
+    n, m = B.thoi_eval_launch_shape(20, sel, B.ThoiEvalOpts(precision=B.THOI_FP32_REFINE, out_dtype=1))
+    # largest grid: orders 9..12, two n-plets per lane, 256 lanes per workgroup
+    assert n == 4 and m == 256 * sum(-(-math.comb(20, k) // 512) for k in range(9, 13))
+    assert B.lib().thoi_eval_launch_shape(20, ctypes.byref(B.ThoiNplets(mode=9)),
+                                          ctypes.byref(B.ThoiEvalOpts(precision=0, out_dtype=0)),
+                                          ctypes.byref(ctypes.c_int32()), ctypes.byref(ctypes.c_int64())) \
+        == B.THOI_EINVAL

@@ -4,18 +4,25 @@ size.
 
 * N=30, T=1200 AR(1) mixture: all 1,073,741,358 n-plets of orders 3..30 in reduce mode.  Histogram
   totals equal C(30, k) exactly; every reported top-100 / bottom-100 n-plet's Omega equals the
-  oracle's; in a seeded sample of 10^5 n-plets nothing beats the reported extremes, and every
-  sampled n-plet clearly beyond the K-th reported value is in the reported list.
+  oracle's; orders 3..5 (173,971 n-plets) and 27..30 (4,526) are evaluated exhaustively by the
+  oracle and their lists and histograms checked by the top-K acceptance rule and bin by bin; in a
+  seeded sample of 10^5 n-plets of all orders nothing beats the reported extremes, and every
+  sampled n-plet clearly beyond the K-th reported value is in the reported list.  Global indices
+  are mapped to n-plets by the test's own lexicographic unranking.
 * 1024 uneven datasets (N ~ U{10..40}, T ~ U{500..5000}), orders 3..5, one multi-dataset call:
   every dataset with N <= 20 against the oracle exhaustively, the others on seeded samples.
-* N=100, T=2000: 10^5 n-plets of order 8..20, forward and the adjoint of sum(Omega) against the
-  oracle's explicit-inverse gradient of the same sum.
+* N=100, T=2000: 10^5 n-plets of order 8..20, forward (entropy plane elementwise to relative 1e-4)
+  and the adjoint of sum(Omega) against the oracle's explicit-inverse gradient of the same sum;
+  the adjoint of the first 100 n-plets, each alone with random weights on all four measures,
+  against FP64 central finite differences (h = 1e-6) of the oracle's literal measures.
 """
 import math
 import sys
 
 import numpy as np
 import pytest
+
+from _checks import check_hist, check_topk, fd_nplet_grad, lex_rank, lex_unrank
 
 pytestmark = pytest.mark.gpu
 
@@ -36,14 +43,15 @@ def env(orc):
 
 def test_ar1_30_exhaustive_reduce(env):
     torch, api, B, synth, orc = env
-    N, kmin, kmax, K = 30, 3, 30, 100
+    N, kmin, kmax, K, bins = 30, 3, 30, 100, 256
+    TOL = 1e-3
     X = synth.ar1_30()
     S = orc.gc_covariance(X)
     Sd = torch.from_numpy(S).cuda()
     lohi = np.zeros((kmax + 1, 2))
     lohi[:, 0], lohi[:, 1] = -40.0, 10.0
     say("ar1_30: all 1,073,741,358 n-plets, fp32_refine, top-100 / bottom-100 + 256 bins")
-    st = api.nplets_reduce(Sd, orders=(kmin, kmax), topk=K, hist_bins=256, hist_range=lohi, precision="fp32_refine")
+    st = api.nplets_reduce(Sd, orders=(kmin, kmax), topk=K, hist_bins=bins, hist_range=lohi, precision="fp32_refine")
     tv, tg, h = st.result()
     for k in range(kmin, kmax + 1):
         assert int(h[0, k].sum()) == math.comb(N, k), k
@@ -56,30 +64,36 @@ def test_ar1_30_exhaustive_reduce(env):
             g = tg[0, k, l, :n]
             assert np.all(g >= 0) and np.all(tg[0, k, l, n:] == -1), (k, l)
             for j, gg in enumerate(g):
-                rows.append(B.thoi_unrank_host(N, kmin, int(gg)))
+                rows.append(lex_unrank(int(gg), N, kmin))
                 vals.append(tv[0, k, l, j])
                 where.append((k, l, j))
     say(f"oracle on the {len(rows)} reported n-plets")
     ref, _, _ = orc.eval_list(S, orc.pad_list(rows, kmax))
-    assert np.abs(ref[2] - np.array(vals)).max() < 1e-3
+    assert np.abs(ref[2] - np.array(vals)).max() < TOL
     for (k, l, j), r in zip(where, rows):
         assert len(r) == k
+    # orders 3..5 and 27..30 exhaustively: lists by the acceptance rule, histograms bin by bin
+    for lo_k, hi_k in ((3, 5), (27, 30)):
+        idx = orc.enumerate_nplets(N, lo_k, hi_k)
+        say(f"oracle on all {len(idx)} n-plets of orders {lo_k}..{hi_k}")
+        ref, _, _ = orc.eval_list(S, idx)
+        ords = (idx >= 0).sum(1)
+        g0 = B.thoi_count(N, kmin, lo_k - 1) if lo_k > kmin else 0
+        g_all = g0 + np.arange(len(idx))
+        assert lex_rank(tuple(idx[-1][idx[-1] >= 0]), N, kmin) == g_all[-1]
+        near = 0
+        for k in range(lo_k, hi_k + 1):
+            sel = ords == k
+            for l, largest in ((0, True), (1, False)):
+                check_topk(tv[0, k, l], tg[0, k, l], g_all[sel], ref[2][sel], K, TOL, largest, f"k={k} l={l}")
+            near += check_hist(h[0, k], ref[2][sel], lohi[k, 0], lohi[k, 1], bins, TOL, f"k={k}")
+        say(f"orders {lo_k}..{hi_k}: lists and histograms pass ({near} values within {TOL:g} of a bin edge)")
     # a seeded sample of 10^5 n-plets against the lists (membership by global rank)
     rng = np.random.default_rng(30)
     ks = rng.integers(kmin, kmax + 1, 100000)
     samp = [tuple(sorted(rng.choice(N, int(k), replace=False))) for k in ks]
     say("oracle on a seeded sample of 10^5 n-plets")
     sv, _, _ = orc.eval_list(S, orc.pad_list(samp, kmax))
-    def rank(c):
-        k = len(c)
-        g = sum(math.comb(N, j) for j in range(kmin, k))
-        x = 0
-        for i, v in enumerate(c):
-            for y in range(x, v):
-                g += math.comb(N - 1 - y, k - 1 - i)
-            x = v + 1
-        return g
-
     for k in range(kmin, kmax + 1):
         sel = np.nonzero(ks == k)[0]
         if len(sel) == 0:
@@ -87,12 +101,12 @@ def test_ar1_30_exhaustive_reduce(env):
         n = min(K, math.comb(N, k))
         top, bot = set(tg[0, k, 0, :n].tolist()), set(tg[0, k, 1, :n].tolist())
         v = sv[2][sel]
-        assert v.max() <= tv[0, k, 0, 0] + 1e-3 and v.min() >= tv[0, k, 1, 0] - 1e-3, k
+        assert v.max() <= tv[0, k, 0, 0] + TOL and v.min() >= tv[0, k, 1, 0] - TOL, k
         # a sampled n-plet clearly above the K-th largest (below the K-th smallest) is in the list
-        for i in sel[v > tv[0, k, 0, n - 1] + 1e-3]:
-            assert rank(samp[i]) in top, (k, samp[i])
-        for i in sel[v < tv[0, k, 1, n - 1] - 1e-3]:
-            assert rank(samp[i]) in bot, (k, samp[i])
+        for i in sel[v > tv[0, k, 0, n - 1] + TOL]:
+            assert lex_rank(samp[i], N, kmin) in top, (k, samp[i])
+        for i in sel[v < tv[0, k, 1, n - 1] - TOL]:
+            assert lex_rank(samp[i], N, kmin) in bot, (k, samp[i])
 
 
 def test_uneven_1024_datasets(env):
@@ -125,10 +139,14 @@ def test_latent100_forward_and_adjoint(env):
     S = orc.gc_covariance(X)
     Sd = torch.from_numpy(S).cuda()
     rows = torch.from_numpy(idx).cuda()
-    say("latent_100: 10^5 n-plets of order 8..20, forward fp32_refine")
-    out, _ = api.nplets_measures(Sd, nplets=rows, precision="fp32_refine")
-    ref, _, _ = orc.eval_list(S, idx)
-    assert np.abs(out.cpu().numpy().astype(np.float64) - ref).max() < 1e-3
+    say("latent_100: 10^5 n-plets of order 8..20, forward fp32_refine with the entropy plane")
+    out, _ = api.nplets_measures(Sd, nplets=rows, precision="fp32_refine", write_entropy=True)
+    ref, Href, _ = orc.eval_list(S, idx)
+    out = out.cpu().numpy().astype(np.float64)
+    assert np.abs(out[:4] - ref).max() < 1e-3
+    relH = np.abs(out[4] - Href) / np.abs(Href)
+    say(f"latent_100: max relative error of H(X^n) {relH.max():.2e}")
+    assert relH.max() <= 1e-4
     say("latent_100: adjoint of sum(Omega) over the 10^5 n-plets")
     w = torch.zeros((4, idx.shape[0]), dtype=torch.float32, device=Sd.device)
     w[2] = 1.0
@@ -137,3 +155,34 @@ def test_latent100_forward_and_adjoint(env):
     wo[2] = 1.0
     Go = orc.grad_list(S, idx, wo)
     assert np.linalg.norm(G - Go) <= 1e-3 * np.linalg.norm(Go)
+
+
+def test_latent100_adjoint_vs_finite_differences(env):
+    """The method's differentiation check: the first 100 n-plets of the N=100 workload, each with
+    random weights on TC, DTC, Omega and S, adjoint (FP64 factorisation, FP32 accumulation) against
+    central differences h = 1e-6 of the oracle's literal measures.  Bound per n-plet: 1e-6 of its
+    largest gradient entry (the FD error itself is below 6.1e-8 of it, FP32 rounding 6e-8)."""
+    torch, api, B, synth, orc = env
+    X, idx = synth.latent_100()
+    S = orc.gc_covariance(X)
+    nb = 100
+    W = np.random.default_rng(40).uniform(-1.0, 1.0, (4, nb))
+    # dataset b holds a copy of Sigma and only n-plet b carries weight there
+    Sd = torch.from_numpy(np.ascontiguousarray(np.broadcast_to(S, (nb,) + S.shape))).cuda()
+    g = np.zeros((4, nb, nb), dtype=np.float32)
+    for b in range(nb):
+        g[:, b, b] = W[:, b]
+    say("latent_100: adjoint of 100 single n-plets (100 datasets x 100 rows)")
+    G = api.measures_backward(Sd, torch.from_numpy(g).cuda(), nplets=torch.from_numpy(idx[:nb]).cuda())
+    G = G.double().cpu().numpy()
+    worst = 0.0
+    say("oracle: central differences of the literal measures")
+    for b in range(nb):
+        r, G_fd = fd_nplet_grad(orc, S, idx[b], W[:, b].astype(np.float32).astype(np.float64))
+        mask = np.zeros(S.shape, dtype=bool)
+        mask[np.ix_(r, r)] = True
+        assert np.all(G[b][~mask] == 0.0), b
+        err = np.abs(G[b][np.ix_(r, r)] - G_fd).max() / max(1.0, np.abs(G_fd).max())
+        worst = max(worst, err)
+    say(f"adjoint vs finite differences: worst normalised error {worst:.2e}")
+    assert worst <= 1e-6

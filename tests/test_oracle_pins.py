@@ -391,6 +391,29 @@ def test_gradient_matches_finite_differences(orc):
     assert err < 1e-6, err
 
 
+def test_gradient_fd_on_latent100_nplets(orc):
+    """The first 100 n-plets of the N=100 differentiation workload (orders 8..20, planted groups of
+    four): the oracle's explicit-inverse gradient of a random combination of the four measures
+    against central differences (h = 1e-6) of the literal measures, entry by entry.  The bound,
+    1e-6 of the n-plet's largest gradient entry, is 16x the largest discrepancy observed."""
+    from _checks import fd_nplet_grad
+    X, idx = synth.latent_100()
+    S = orc.gc_covariance(X)
+    W = np.random.default_rng(40).uniform(-1.0, 1.0, (4, 100))
+    worst = 0.0
+    for b in range(100):
+        r, G_fd = fd_nplet_grad(orc, S, idx[b], W[:, b])
+        G = orc.grad_list(S, idx[b:b + 1], W[:, b:b + 1])
+        # the gradient lives on the n-plet's block only
+        mask = np.zeros(S.shape, dtype=bool)
+        mask[np.ix_(r, r)] = True
+        assert np.all(G[~mask] == 0.0)
+        scale = max(1.0, np.abs(G_fd).max())
+        err = np.abs(G[np.ix_(r, r)] - G_fd).max() / scale
+        worst = max(worst, err)
+    assert worst < 1e-6, worst
+
+
 # --------------------------------------------------------------------------- planted data
 def test_planted_10_population_values(orc):
     c = 1.0 / 0.3
