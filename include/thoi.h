@@ -172,6 +172,30 @@ thoi_status thoi_nplets_eval(const double* Sigma, int64_t D, int32_t N, const th
                              void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): thoi_nplets_eval without a workspace argument.  Same
+ * arguments (minus ws), checks, kernels and results as thoi_nplets_eval; the workspace is a
+ * fixed device array of THOI_NOALLOC_SCRATCH_BYTES owned by the library, one per GPU, held until
+ * the process ends.  The call allocates nothing (no hipMalloc, no stream or event creation): all
+ * of its kernels go to `stream`, one after the other.
+ *   status: device int32 or NULL; receives the call's device status word (THOI_OK, or the
+ *           thoi_status a kernel raised: THOI_EINVAL_DATA for bad LIST / MASK rows,
+ *           THOI_EWORKSPACE when the FP64 refinement queue overflowed) once the call's kernels
+ *           have run.
+ * Errors: THOI_EWORKSPACE, before anything is enqueued, when the call needs more workspace than
+ * THOI_NOALLOC_SCRATCH_BYTES (thoi_workspace_bytes(THOI_WS_EVAL, D, 0, N, sel, opts) tells);
+ * THOI_EHIP when the array's address cannot be obtained on the stream's device; otherwise those
+ * of thoi_nplets_eval.
+ * Every call on one GPU uses that GPU's array, which keeps what the last call left in it (each
+ * call clears what it needs at its start).  Calls that overlap in time on one GPU (two streams,
+ * two host threads) race on it and give undefined results: the caller serialises them.
+ */
+#define THOI_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+thoi_status thoi_nplets_eval_noalloc(const double* Sigma, int64_t D, int32_t N, const thoi_nplets* sel,
+                                     const thoi_eval_opts* opts, void* out, uint8_t* flags,
+                                     int32_t* status, void* stream);
+
+/*
  * Host, pure: the launches thoi_nplets_eval would enqueue for the evaluation engines of this
  * selection on one dataset (the class launches and the large-order engine; not the small
  * bookkeeping kernels), and the largest number of work-items along x among them.  Every grid is

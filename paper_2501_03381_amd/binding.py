@@ -28,12 +28,14 @@ THOI_OBJ_MEAN, THOI_OBJ_PAIRED_EFFECT = 0, 1
 THOI_MAX_N_RANGE = 62
 THOI_MAX_N = 128
 THOI_MAX_K = 64
+THOI_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 EXPORTS = [
     "thoi_copulize", "thoi_cov", "thoi_nplets_eval", "thoi_nplets_eval_backward", "thoi_reduce_init",
     "thoi_workspace_bytes", "thoi_ws_status_offset", "thoi_count", "thoi_unrank_host", "thoi_bias_offsets",
     "thoi_status_string", "thoi_version", "thoi_nplets_eval_multi", "thoi_multi_offsets",
     "thoi_multi_workspace_bytes", "thoi_objective", "thoi_objective_workspace_bytes", "thoi_eval_launch_shape",
+    "thoi_nplets_eval_noalloc",
 ]
 
 
@@ -99,6 +101,7 @@ def lib():
     L.thoi_cov.argtypes = [P, I32, I64, I64, I64, P, P, SZ, P]
     L.thoi_nplets_eval.argtypes = [P, I64, I32, NP, OP, P, P, P, SZ, P]
     L.thoi_nplets_eval_backward.argtypes = [P, I64, I32, NP, OP, P, P, P, SZ, P]
+    L.thoi_nplets_eval_noalloc.argtypes = [P, I64, I32, NP, OP, P, P, P, P]
     L.thoi_reduce_init.argtypes = [ctypes.POINTER(ThoiReduce), I64, I32, P]
     L.thoi_workspace_bytes.argtypes = [I32, I64, I64, I32, NP, OP]
     L.thoi_workspace_bytes.restype = SZ
@@ -123,7 +126,7 @@ def lib():
     L.thoi_version.restype = ctypes.c_char_p
     for fn in ("thoi_copulize", "thoi_cov", "thoi_nplets_eval", "thoi_nplets_eval_backward", "thoi_reduce_init",
                "thoi_unrank_host", "thoi_bias_offsets", "thoi_nplets_eval_multi", "thoi_multi_offsets",
-               "thoi_objective", "thoi_eval_launch_shape"):
+               "thoi_objective", "thoi_eval_launch_shape", "thoi_nplets_eval_noalloc"):
         getattr(L, fn).restype = I32
     _lib = L
     return L
@@ -146,6 +149,11 @@ def thoi_cov(Z, z_dtype, D, T, N, Sigma, ws, ws_bytes, stream):
 def thoi_nplets_eval(Sigma, D, N, sel: ThoiNplets, opts: ThoiEvalOpts, out, flags, ws, ws_bytes, stream):
     check("thoi_nplets_eval", lib().thoi_nplets_eval(Sigma, D, N, ctypes.byref(sel), ctypes.byref(opts), out, flags,
                                                      ws, ws_bytes, stream))
+
+
+def thoi_nplets_eval_noalloc(Sigma, D, N, sel: ThoiNplets, opts: ThoiEvalOpts, out, flags, status, stream):
+    check("thoi_nplets_eval_noalloc", lib().thoi_nplets_eval_noalloc(Sigma, D, N, ctypes.byref(sel),
+                                                                     ctypes.byref(opts), out, flags, status, stream))
 
 
 def thoi_nplets_eval_backward(Sigma, D, N, sel: ThoiNplets, opts: ThoiEvalOpts, grad_out, grad_Sigma, ws, ws_bytes,

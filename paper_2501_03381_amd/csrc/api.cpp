@@ -112,7 +112,9 @@ int64_t count_orders(int N, int kmin, int kmax)
 bool valid_dtype(int32_t t) { return t == THOI_DTYPE_F64 || t == THOI_DTYPE_F32; }
 constexpr size_t kLdsLimit = 160 * 1024;
 
-thoi_status check_eval(const double* Sigma, int64_t D, int32_t N, const thoi_nplets* sel, const thoi_eval_opts* opts,
+}  // namespace
+
+thoi_status thoi::check_eval(const double* Sigma, int64_t D, int32_t N, const thoi_nplets* sel, const thoi_eval_opts* opts,
                        bool forward, const void* out)
 {
     if (!sel || !opts) return THOI_EINVAL;
@@ -185,8 +187,6 @@ thoi_status check_eval(const double* Sigma, int64_t D, int32_t N, const thoi_npl
     if (!forward && backward_lds_bytes(N, sel) > kLdsLimit) return THOI_EUNSUPPORTED;
     return THOI_OK;
 }
-
-}  // namespace
 
 extern "C" {
 

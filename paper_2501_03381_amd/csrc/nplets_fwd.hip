@@ -383,6 +383,7 @@ struct Plan {
     int wkmax;
     int seg_tiles, wave_tile;
     int64_t seg_cap;
+    bool serial;     // every launch on the caller's stream (no side streams)
 };
 
 // Grids are kept well below the dispatch limit of 2^32 work-items along x: a class grid by
@@ -574,7 +575,7 @@ void launch_engines(EvalArgs& a, const Plan& P, const RedArgs& red, hipStream_t 
     // the class launches are independent: fan them out over side streams
     int nl = P.wblk ? 1 : 0;
     for (int c = 0; c < ncls; ++c) nl += P.nblk[c] != 0;
-    FanScope fan(s, nl);
+    FanScope fan(s, P.serial ? 1 : nl);
     int b = 0;
     const int* order = sizeof(F) == 4 ? kF32LaunchOrder : kF64LaunchOrder;
     for (int oc = 0; oc < ncls; ++oc) {
@@ -663,7 +664,7 @@ size_t eval_lds_bytes(int32_t N, const thoi_nplets* sel, const thoi_eval_opts* o
 }
 
 thoi_status launch_eval(const double* Sigma, int64_t D, int32_t N, const thoi_nplets* sel, const thoi_eval_opts* opts,
-                        void* out, uint8_t* flags, void* ws, size_t ws_bytes, hipStream_t s)
+                        void* out, uint8_t* flags, void* ws, size_t ws_bytes, hipStream_t s, bool serial)
 {
     const EvalWs w = eval_layout(D, N, sel, opts);
     if (ws == nullptr || ws_bytes < w.total) return THOI_EWORKSPACE;
@@ -720,12 +721,14 @@ thoi_status launch_eval(const double* Sigma, int64_t D, int32_t N, const thoi_np
     if (D == 0 || a.B == 0) return hip_status(hipGetLastError());
 
     if (opts->precision == THOI_FP64) {
-        const Plan P = make_plan<double>(N, sel, reduce, opts->precision, opts->seg_tiles);
+        Plan P = make_plan<double>(N, sel, reduce, opts->precision, opts->seg_tiles);
+        P.serial = serial;
         a.seg_tiles = P.seg_tiles;
         a.wave_tile = P.wave_tile;
         launch_forward<double>(a, sel, P, red, w, base, s);
     } else {
-        const Plan P = make_plan<float>(N, sel, reduce, opts->precision, opts->seg_tiles);
+        Plan P = make_plan<float>(N, sel, reduce, opts->precision, opts->seg_tiles);
+        P.serial = serial;
         a.seg_tiles = P.seg_tiles;
         a.wave_tile = P.wave_tile;
         launch_forward<float>(a, sel, P, red, w, base, s);

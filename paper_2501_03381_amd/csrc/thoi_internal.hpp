@@ -67,9 +67,13 @@ size_t copulize_ws_bytes(int64_t D, int64_t T, int64_t N);
 thoi_status launch_cov(const void* Z, int32_t z_dtype, int64_t D, int64_t T, int64_t N, double* Sigma,
                        void* ws, hipStream_t s);
 size_t cov_ws_bytes(int64_t D, int64_t T, int64_t N);
+// serial: every launch goes to `s` (no side streams are created or used)
 thoi_status launch_eval(const double* Sigma, int64_t D, int32_t N, const thoi_nplets* sel,
                         const thoi_eval_opts* opts, void* out, uint8_t* flags, void* ws, size_t ws_bytes,
-                        hipStream_t s);
+                        hipStream_t s, bool serial = false);
+// Host argument checks of thoi_nplets_eval (forward) and thoi_nplets_eval_backward (api.cpp).
+thoi_status check_eval(const double* Sigma, int64_t D, int32_t N, const thoi_nplets* sel,
+                       const thoi_eval_opts* opts, bool forward, const void* out);
 size_t eval_ws_bytes(int64_t D, int32_t N, const thoi_nplets* sel, const thoi_eval_opts* opts);
 size_t eval_lds_bytes(int32_t N, const thoi_nplets* sel, const thoi_eval_opts* opts);
 void eval_launch_shape(int32_t N, const thoi_nplets* sel, const thoi_eval_opts* opts, int32_t* n_launches,

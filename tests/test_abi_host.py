@@ -95,6 +95,27 @@ def test_bias_offsets_match_oracle(B, orc):
             assert abs(eta - orc.bias_eta(k, T)) < 1e-11
 
 
+def test_noalloc_scratch_limit_checked_before_launch(B):
+    """The workspace-free evaluation states its fixed scratch size in the header and rejects a call
+    that needs more before touching the device (no GPU needed: the check precedes every HIP call)."""
+    text = open(HEADER).read()
+    m = re.search(r"#define THOI_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == B.THOI_NOALLOC_SCRATCH_BYTES
+    L = B.lib()
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: the calls below fail their host checks
+    sel = B.ThoiNplets(mode=B.THOI_SEL_RANGE, kmin=3, kmax=20, g_begin=0, g_count=1048365)
+    opts = B.ThoiEvalOpts(precision=B.THOI_FP32_REFINE, out_dtype=B.THOI_DTYPE_F32, vif_tau=1e3)
+    D = 8                             # refinement queue of 8 x 1,048,365 positions: 67 MB
+    assert B.thoi_workspace_bytes(B.THOI_WS_EVAL, D, 0, 20, sel, opts) > B.THOI_NOALLOC_SCRATCH_BYTES
+    assert L.thoi_nplets_eval_noalloc(fake, D, 20, ctypes.byref(sel), ctypes.byref(opts), fake, None, None,
+                                      None) == B.THOI_EWORKSPACE
+    # argument errors come first, exactly as for thoi_nplets_eval
+    assert L.thoi_nplets_eval_noalloc(fake, 1, 20, ctypes.byref(sel), ctypes.byref(opts), None, None, None,
+                                      None) == B.THOI_EINVAL
+    assert L.thoi_nplets_eval_noalloc(fake, 1, 20, ctypes.byref(B.ThoiNplets(mode=7)), ctypes.byref(opts), fake,
+                                      None, None, None) == B.THOI_EINVAL
+
+
 def test_argument_errors_return_before_launch(B):
     L = B.lib()
     sel = B.ThoiNplets(mode=B.THOI_SEL_RANGE, kmin=3, kmax=20, g_begin=0, g_count=10)
