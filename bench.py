@@ -384,6 +384,13 @@ def bench_paired(torch, np, api, B, synth, dev, args):
             "cpu_baseline": cpu}
 
 
+def adjoint_flops(k):
+    """Algorithmic flops of the adjoint of one n-plet of order k: Cholesky, triangular inverse and
+    P = W^T W in FP64 ((k^3-k)/6 + (k^3-k)/6 + k(k+1)(k+2)/6 FMA) and the k(k+1)/2 length-k dot
+    products of Z^2 in FP32 (k^2(k+1)/2 FMA); the two FMA counts are equal."""
+    return 2 * ((k ** 3 - k) // 3 + k * (k + 1) * (k + 2) // 6 + k * k * (k + 1) // 2)
+
+
 def bench_grad(torch, np, api, B, synth, dev, args):
     """N=100, T=2000 latent model: 10^5 n-plets of order U{8..20}; forward (Omega, S, TC, DTC) plus
     the adjoint d(sum Omega)/d Sigma."""
@@ -395,9 +402,16 @@ def bench_grad(torch, np, api, B, synth, dev, args):
     fwd = kernel_ms(torch, lambda st: api.nplets_measures(Sigma, nplets=I, precision="fp32_refine", check=False),
                     reps=5)
     bwd = kernel_ms(torch, lambda st: api.measures_backward(Sigma, g, nplets=I), reps=5)
+    kk = (idx >= 0).sum(axis=1).astype(np.int64)
+    fl = int(adjoint_flops(kk).sum())
+    ach = fl / (bwd * 1e-3) / 1e12
     return {"workload": "latent100_grad: N=100, T=2000, seed 4, 1e5 n-plets of order 8..20", "metric": "n-plets/s",
             "value": idx.shape[0] / (fwd * 1e-3), "unit": "n-plets/s", "forward_ms": fwd, "backward_ms": bwd,
-            "backward_nplets_per_s": idx.shape[0] / (bwd * 1e-3)}
+            "backward_nplets_per_s": idx.shape[0] / (bwd * 1e-3),
+            "backward_roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": 78.6, "unit": "TFLOP/s",
+                                  "frac": round(ach / 78.6, 4), "flops_per_call": fl,
+                                  "note": "whole adjoint call (bucketing + lane classes); peak = FP64 vector, "
+                                          "also the non-packed FP32 rate"}}
 
 
 def bench_classes(torch, np, api, B, synth, dev, args):

@@ -209,7 +209,8 @@ thoi_status thoi_eval_launch_shape(int32_t N, const thoi_nplets* sel, const thoi
 /*
  * Adjoint of thoi_nplets_eval: grad_Sigma[d] += sum_b sum_m grad_out[m][d][b] *
  * d measure_m(b, d) / d Sigma_d, with the entries of Sigma treated as
- * independent (the result is symmetric).  FP64 factorisation, FP32 accumulation.
+ * independent (the result is symmetric).  FP64 factorisation, inverse and P = R_S^-1; the
+ * quadratic part (P diag(1/p) P, from the unit-diagonal rescaling of P) and the accumulation in FP32.
  *   grad_out: device [4][D][B] FP32 (planes TC, DTC, Omega, S).
  *   grad_Sigma: device [D][N][N] FP32, accumulated.
  * The bias correction adds constants and has no gradient.  n-plets whose

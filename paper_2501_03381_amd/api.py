@@ -398,7 +398,7 @@ class NpletsMeasures(torch.autograd.Function):
     """(TC, DTC, Omega, S) of the selected n-plets as a differentiable function of Sigma.
 
     forward runs thoi_nplets_eval; backward runs the hand-written adjoint
-    thoi_nplets_eval_backward (FP64 factorisation, FP32 accumulation).
+    thoi_nplets_eval_backward (FP64 factorisation and inverse, FP32 quadratic part and accumulation).
     """
 
     @staticmethod

@@ -15,41 +15,40 @@
 // c_D = w_DTC - w_O + w_S:
 //   G_ij = { c_T/2 (delta_ij - P_ij) + c_D/2 (P_ij - (P diag(1/p) P)_ij) } / sqrt(d_i d_j).
 //
-// Work decomposition: one wavefront per n-plet (FP64, runtime order, so LIST rows need no
-// bucketing); P = W^T W from the triangular inverse W = L^-1 that the factorisation leaves in
-// LDS.  Each workgroup accumulates its n-plets' contributions in an LDS N x N FP32 tile (lane i
-// owns row c_i, so the adds of one wavefront never collide) and flushes it once with hardware
-// float atomics.
-#include "nplets_common.hpp"
+// Orders up to kBwdLaneMax run on the lane engine (one lane per n-plet, registers;
+// nplets_bwd_lane.hpp), larger orders on the wave engine below (one wavefront per n-plet, LDS).
+// LIST / MASK rows are first bucketed by order on the device.  This file holds the wave engine
+// and the host side.
+#include "nplets_bwd.hpp"
+#include "nplets_fwd_common.hpp"
 
 namespace thoi {
 namespace {
 
-constexpr int64_t kBwdTileMin = 16;     // n-plets per workgroup, bounds of the host's choice
-constexpr int64_t kBwdTileMax = 4096;
+constexpr int kCus = 256;
 constexpr int64_t kLdsPerCu = 160 * 1024;
-constexpr int64_t kCus = 256;
+constexpr size_t kLdsLimit = 160 * 1024;
 
-struct BwdArgs {
-    const double* Sigma;
-    int32_t N, D;
-    int64_t B;
-    const float* grad_out;      // [4][D][B]
-    float* grad_Sigma;          // [D][N][N]
-    int32_t mode;
-    int32_t kmin, kmax;         // RANGE
-    int64_t g_begin;
-    int64_t ostart[THOI_MAX_K + 2];
-    const int32_t* idx;
-    int32_t kmax_list;
-    const uint64_t* mask;
-    int32_t ks;                 // LDS row stride (>= largest order + 1)
-    int64_t tile;               // n-plets per workgroup
-};
+__device__ __forceinline__ bool bwd_wave_weights(const BwdArgs& a, int d, int64_t pos, double& cT, double& cD)
+{
+    const int64_t o = (int64_t)d * a.B + pos;
+    const int64_t plane = (int64_t)a.D * a.B;
+    const double wTC = a.grad_out[o], wDTC = a.grad_out[plane + o];
+    const double wO = a.grad_out[2 * plane + o], wS = a.grad_out[3 * plane + o];
+    cT = wTC + wO + wS;
+    cD = wDTC - wO + wS;
+    return cT != 0.0 || cD != 0.0;
+}
 
+// ------------------------------------------------------------------------------------------------
+// Wave engine: orders above the lane engine's, one wavefront per n-plet, FP64 in LDS.
+// grid (workgroups, D), block 64; each workgroup walks n-plets blockIdx.x, + gridDim.x, ... of
+// the slots [s0, s1): RANGE positions [s0_range, s1_range) (the orders above the lane engine);
+// LIST / MASK slots of perm from the bucket of order lane_max + 1 on.
 // LDS: sIsd [N] f64 | sBin [N*64] u64 (RANGE) | sM [64*ks] f64 | sP [64*ks] f64 | sInv [64] f64 |
 //      sAcc [N*N] f32 | cidx [64] i32
-__host__ __device__ inline size_t bwd_lds_bytes(int N, int ks, bool range)
+// ------------------------------------------------------------------------------------------------
+__host__ __device__ inline size_t bwd_wave_lds_bytes(int N, int ks, bool range)
 {
     size_t off = (size_t)N * 8 + (range ? (size_t)N * 64 * 8 : 0);
     off += 2 * (size_t)64 * ks * 8 + 64 * 8;
@@ -58,10 +57,10 @@ __host__ __device__ inline size_t bwd_lds_bytes(int N, int ks, bool range)
 }
 
 template <int MODE>
-__global__ __launch_bounds__(64) void k_backward(BwdArgs a)
+__global__ __launch_bounds__(64) void k_bwd_wave(BwdArgs a, int ks, int64_t s0_range, int64_t s1_range)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int N = a.N, ks = a.ks;
+    const int N = a.N;
     const int d = blockIdx.y;
     const int lane = threadIdx.x;
     double* sIsd = reinterpret_cast<double*>(smem);
@@ -73,6 +72,13 @@ __global__ __launch_bounds__(64) void k_backward(BwdArgs a)
     int* cidx = reinterpret_cast<int*>(sAcc + N * N);
     __shared__ int sk;
 
+    int64_t s0 = s0_range, s1 = s1_range;
+    if constexpr (MODE != THOI_SEL_RANGE) {
+        s0 = a.lbase[a.lane_max + 1];
+        s1 = a.lbase[THOI_MAX_K + 1];
+    }
+    if (s0 + (int64_t)blockIdx.x >= s1) return;   // uniform: nothing for this workgroup
+
     const double* Sig = a.Sigma + (int64_t)d * N * N;
     for (int j = lane; j < N; j += 64) {
         const double dj = Sig[(int64_t)j * N + j];
@@ -82,16 +88,11 @@ __global__ __launch_bounds__(64) void k_backward(BwdArgs a)
     if constexpr (MODE == THOI_SEL_RANGE) stage_binomials(N, 64, sBin);
     __syncthreads();
 
-    const int64_t b0 = (int64_t)blockIdx.x * a.tile;
-    const int64_t b1 = b0 + a.tile < a.B ? b0 + a.tile : a.B;
     bool touched = false;
-    for (int64_t pos = b0; pos < b1; ++pos) {
-        const int64_t o = (int64_t)d * a.B + pos;
-        const float wTC = a.grad_out[o], wDTC = a.grad_out[(int64_t)a.D * a.B + o];
-        const float wO = a.grad_out[2 * (int64_t)a.D * a.B + o], wS = a.grad_out[3 * (int64_t)a.D * a.B + o];
-        const double cT = (double)wTC + (double)wO + (double)wS;
-        const double cD = (double)wDTC - (double)wO + (double)wS;
-        if (cT == 0.0 && cD == 0.0) continue;   // uniform across the wave
+    for (int64_t slot = s0 + blockIdx.x; slot < s1; slot += gridDim.x) {
+        const int64_t pos = MODE == THOI_SEL_RANGE ? slot : a.perm[slot];
+        double cT, cD;
+        if (!bwd_wave_weights(a, d, pos, cT, cD)) continue;   // uniform across the wave
         if (lane == 0) {
             int k = 0;
             if constexpr (MODE == THOI_SEL_RANGE) {
@@ -101,25 +102,15 @@ __global__ __launch_bounds__(64) void k_backward(BwdArgs a)
                 unrank_lex_rt((uint64_t)(g - a.ostart[k]), N, k, sBin, 64, cidx);
             } else if constexpr (MODE == THOI_SEL_LIST) {
                 const int32_t* row = a.idx + pos * a.kmax_list;
-                bool ok = true;
-                int prev = -1;
-                while (k < a.kmax_list && row[k] >= 0) {
-                    ok = ok && row[k] > prev && row[k] < N;
-                    prev = row[k];
-                    cidx[k] = row[k];
-                    ++k;
-                }
-                if (!ok || k > 64) k = -1;   // invalid rows contribute nothing
+                while (k < a.kmax_list && row[k] >= 0) { cidx[k] = row[k]; ++k; }
             } else {
                 uint64_t m = a.mask[pos];
-                if (N < 64 && (m >> N) != 0) m = 0, k = -1;
                 while (m) { cidx[k++] = __builtin_ctzll(m); m &= m - 1; }
             }
             sk = k;
         }
         __syncthreads();
         const int k = sk;
-        if (k <= 0) { __syncthreads(); continue; }
         // correlation sub-matrix rows, lane i owns row i
         if (lane < k) {
             const int ci = cidx[lane];
@@ -130,7 +121,7 @@ __global__ __launch_bounds__(64) void k_backward(BwdArgs a)
             sM[lane * ks + lane] = 1.0;
         }
         __syncthreads();
-        // Cholesky (right-looking) and W = L^-1: same steps as the forward wave engine
+        // Cholesky (right-looking) and W = L^-1
         bool ok = true;
         for (int j = 0; j < k; ++j) {
             const double p = sM[j * ks + j];
@@ -145,7 +136,7 @@ __global__ __launch_bounds__(64) void k_backward(BwdArgs a)
             }
             __syncthreads();
         }
-        if (!ok) { __syncthreads(); continue; }   // not positive definite: no contribution
+        if (!ok) continue;   // not positive definite: no contribution (uniform)
         if (lane < k) {
             const int j = lane;
             const double wjj = sInv[j];
@@ -168,8 +159,7 @@ __global__ __launch_bounds__(64) void k_backward(BwdArgs a)
             }
         }
         __syncthreads();
-        // U = P diag(1/p) in the rows of sM (W is no longer needed): one reciprocal per column,
-        // then (P diag(1/p) P)_ij = sum_m U_im P_jm (P symmetric; row j is the same for every lane)
+        // U = P diag(1/p) in the rows of sM, then (P diag(1/p) P)_ij = sum_m U_im P_jm
         if (lane < k) sInv[lane] = 1.0 / sP[lane * ks + lane];
         __syncthreads();
         if (lane < k) {
@@ -201,38 +191,169 @@ __global__ __launch_bounds__(64) void k_backward(BwdArgs a)
     }
 }
 
+// ------------------------------------------------------------------------------------------------
+// Host side
+// ------------------------------------------------------------------------------------------------
+int bwd_class_of(int k)
+{
+    int c = 0;
+    while (c < kBwdNClasses - 1 && k > kBwdClasses[c].hi) ++c;
+    return c;
+}
+
+// Largest order of the lane engine for N variables: its staged FP64 matrix and accumulator tile
+// must fit in LDS (N <= 120); otherwise every order goes to the wave engine.
+int bwd_lane_max(int N) { return bwd_lane_lds_bytes(N, kBwdLaneMax) <= kLdsLimit ? kBwdLaneMax : 0; }
+
+void bwd_lane_launch(int cls, const BwdArgs& a, const BwdTiles& t, int64_t ntiles, dim3 grid, size_t lds,
+                     hipStream_t s)
+{
+    if (cls < kBwdNClasses - 1) bwd_lane_launch_lo(cls, a, t, ntiles, grid, lds, s);
+    else bwd_lane_launch_hi(cls, a, t, ntiles, grid, lds, s);
+}
+
+int bwd_lane_blocks_per_cu(int cls, size_t lds)
+{
+    return cls < kBwdNClasses - 1 ? bwd_lane_blocks_per_cu_lo(cls, lds) : bwd_lane_blocks_per_cu_hi(cls, lds);
+}
+
+struct BwdWs {
+    size_t korder_off, cnt_off, base_off, blk0_off, cursor_off, perm_off, total;
+};
+
+BwdWs bwd_layout(const thoi_nplets* sel)
+{
+    BwdWs w{};
+    if (sel->mode == THOI_SEL_RANGE) return w;   // RANGE needs no workspace
+    size_t off = kWsHeader;
+    const int64_t B = sel->B;
+    w.korder_off = off; off = align_up(off + (size_t)B, 256);
+    w.cnt_off = off; off = align_up(off + kListOrders * 8, 256);
+    w.base_off = off; off = align_up(off + kListOrders * 8, 256);
+    w.blk0_off = off; off = align_up(off + kListOrders * 8, 256);
+    w.cursor_off = off; off = align_up(off + kListOrders * 8, 256);
+    w.perm_off = off; off = align_up(off + (size_t)B * 8, 256);
+    w.total = off;
+    return w;
+}
+
+void launch_bwd_engines(BwdArgs& a, const thoi_nplets* sel, hipStream_t s)
+{
+    const int N = a.N;
+    const int64_t D = a.D;
+    const int lane_max = a.lane_max;
+    const bool range = a.mode == THOI_SEL_RANGE;
+    BwdTiles tabs[kBwdNClasses] = {};
+    int64_t ntiles[kBwdNClasses] = {0};
+    int64_t wave_s0 = 0, wave_cnt = 0;
+    int wave_kmax = 0;
+    if (range) {
+        int64_t g = 0;
+        const int64_t gb = sel->g_begin, ge = sel->g_begin + sel->g_count;
+        bool wave_start = false;
+        for (int k = sel->kmin; k <= sel->kmax; ++k) {
+            const int64_t ck = (int64_t)binom_u64(N, k);
+            const int64_t lo = gb > g ? gb : g, hi = ge < g + ck ? ge : g + ck;
+            if (hi > lo) {
+                if (k <= lane_max) {
+                    const int c = bwd_class_of(k);
+                    BwdPiece p{};
+                    p.k = k;
+                    p.first = lo - g;
+                    p.pos0 = lo - gb;
+                    p.cnt = hi - lo;
+                    p.tile0 = ntiles[c];
+                    ntiles[c] += (p.cnt + kBwdTile - 1) / kBwdTile;
+                    tabs[c].p[tabs[c].n++] = p;
+                } else {
+                    if (!wave_start) { wave_s0 = lo - gb; wave_start = true; }
+                    wave_cnt += hi - lo;
+                    wave_kmax = k;
+                }
+            }
+            g += ck;
+        }
+    } else {
+        const int kcap = sel_kmax(sel, N);
+        for (int c = 0; c < kBwdNClasses; ++c) {
+            if (kBwdClasses[c].lo <= kcap && kBwdClasses[c].lo <= lane_max) ntiles[c] = (a.B + kBwdTile - 1) / kBwdTile;
+        }
+        if (kcap > lane_max) { wave_cnt = a.B; wave_kmax = kcap; }
+    }
+    int nl = wave_cnt > 0 ? 1 : 0;
+    for (int c = 0; c < kBwdNClasses; ++c) nl += ntiles[c] > 0;
+    FanScope fan(s, nl);
+    int b = 0;
+    for (int c = kBwdNClasses - 1; c >= 0; --c) {   // longest lanes first
+        if (ntiles[c] == 0) continue;
+        const size_t lds = bwd_lane_lds_bytes(N, range ? kBwdClasses[c].hi : 0);
+        // persistent: one round of workgroups (registers and LDS decide how many a CU holds),
+        // shared among the datasets
+        const int64_t res = (int64_t)kCus * bwd_lane_blocks_per_cu(c, lds);
+        const int64_t per_d = (res + D - 1) / D;
+        const int64_t gx = ntiles[c] < per_d ? ntiles[c] : per_d;
+        bwd_lane_launch(c, a, tabs[c], ntiles[c], dim3((unsigned)gx, (unsigned)D), lds, fan.stream(b++));
+    }
+    if (wave_cnt > 0) {
+        const int ks = (wave_kmax < 64 ? wave_kmax : 64) + 1;
+        const size_t lds = bwd_wave_lds_bytes(N, ks, range);
+        const int64_t per_cu = kLdsPerCu / (int64_t)lds > 0 ? kLdsPerCu / (int64_t)lds : 1;
+        const int64_t per_d = (kCus * per_cu + D - 1) / D;
+        const int64_t gx = wave_cnt < per_d ? wave_cnt : per_d;
+        const dim3 grid((unsigned)gx, (unsigned)D);
+        if (a.mode == THOI_SEL_RANGE)
+            hipLaunchKernelGGL(k_bwd_wave<THOI_SEL_RANGE>, grid, dim3(64), lds, fan.stream(b++), a, ks, wave_s0,
+                               wave_s0 + wave_cnt);
+        else if (a.mode == THOI_SEL_LIST)
+            hipLaunchKernelGGL(k_bwd_wave<THOI_SEL_LIST>, grid, dim3(64), lds, fan.stream(b++), a, ks, (int64_t)0,
+                               (int64_t)0);
+        else
+            hipLaunchKernelGGL(k_bwd_wave<THOI_SEL_MASK>, grid, dim3(64), lds, fan.stream(b++), a, ks, (int64_t)0,
+                               (int64_t)0);
+    }
+}
+
 }  // namespace
 
 size_t backward_ws_bytes(int64_t D, int32_t N, const thoi_nplets* sel, const thoi_eval_opts* opts)
 {
-    (void)D; (void)N; (void)sel; (void)opts;
-    return 0;
+    (void)D; (void)N; (void)opts;
+    return bwd_layout(sel).total;
 }
 
 size_t backward_lds_bytes(int32_t N, const thoi_nplets* sel)
 {
-    const int kmax = sel->mode == THOI_SEL_RANGE ? sel->kmax : (sel->mode == THOI_SEL_LIST ? sel->kmax_list : N);
-    const int ks = (kmax < 64 ? kmax : 64) + 1;
-    return bwd_lds_bytes(N, ks, sel->mode == THOI_SEL_RANGE);
+    const bool range = sel->mode == THOI_SEL_RANGE;
+    const int kmax = range ? sel->kmax : (sel->mode == THOI_SEL_LIST ? sel->kmax_list : N);
+    const int lane_max = bwd_lane_max(N);
+    size_t need = lane_max > 0 ? bwd_lane_lds_bytes(N, range ? kBwdLaneMax : 0) : 0;
+    if (kmax > lane_max) {
+        const int ks = (kmax < 64 ? kmax : 64) + 1;
+        const size_t w = bwd_wave_lds_bytes(N, ks, range);
+        need = need > w ? need : w;
+    }
+    return need;
 }
 
 thoi_status launch_backward(const double* Sigma, int64_t D, int32_t N, const thoi_nplets* sel,
                             const thoi_eval_opts* opts, const float* grad_out, float* grad_Sigma, void* ws,
                             size_t ws_bytes, hipStream_t s)
 {
-    (void)opts; (void)ws; (void)ws_bytes;
+    (void)opts;
+    const BwdWs w = bwd_layout(sel);
+    if (w.total > 0 && (ws == nullptr || ws_bytes < w.total)) return THOI_EWORKSPACE;
     BwdArgs a{};
     a.Sigma = Sigma;
     a.N = N;
     a.D = (int32_t)D;
-    a.B = sel->mode == THOI_SEL_RANGE ? sel->g_count : sel->B;
+    a.B = sel_B(sel);
     a.grad_out = grad_out;
     a.grad_Sigma = grad_Sigma;
     a.mode = sel->mode;
+    a.lane_max = bwd_lane_max(N);
     a.idx = sel->idx;
     a.kmax_list = sel->kmax_list;
     a.mask = sel->mask;
-    int kmax;
     if (sel->mode == THOI_SEL_RANGE) {
         a.kmin = sel->kmin;
         a.kmax = sel->kmax;
@@ -242,30 +363,49 @@ thoi_status launch_backward(const double* Sigma, int64_t D, int32_t N, const tho
             a.ostart[k] = g;
             if (k <= sel->kmax) g += (int64_t)binom_u64(N, k);
         }
-        kmax = sel->kmax;
-    } else if (sel->mode == THOI_SEL_LIST) {
-        kmax = sel->kmax_list;
-    } else {
-        kmax = N;
     }
-    a.ks = (kmax < 64 ? kmax : 64) + 1;
     if (D == 0 || a.B == 0) return THOI_OK;
-    const size_t lds = bwd_lds_bytes(N, a.ks, sel->mode == THOI_SEL_RANGE);
-    // one round of workgroups: as many per dataset as the LDS footprint lets the CUs hold at once
-    // (each workgroup flushes its accumulator tile once, so fewer, longer workgroups also mean
-    // fewer atomics)
-    const int64_t per_cu = (int64_t)(kLdsPerCu / (int64_t)(lds > 0 ? lds : 1));
-    const int64_t resident = kCus * (per_cu > 0 ? per_cu : 1);
-    const int64_t per_d = (resident + D - 1) / D;
-    int64_t tile = (a.B + per_d - 1) / per_d;
-    tile = tile < kBwdTileMin ? kBwdTileMin : (tile > kBwdTileMax ? kBwdTileMax : tile);
-    a.tile = tile;
-    const int64_t nblk = (a.B + tile - 1) / tile;
-    if (nblk > 0x7fffffff) return THOI_EUNSUPPORTED;
-    dim3 grid((unsigned)nblk, (unsigned)D);
-    if (sel->mode == THOI_SEL_RANGE) hipLaunchKernelGGL(k_backward<THOI_SEL_RANGE>, grid, dim3(64), lds, s, a);
-    else if (sel->mode == THOI_SEL_LIST) hipLaunchKernelGGL(k_backward<THOI_SEL_LIST>, grid, dim3(64), lds, s, a);
-    else hipLaunchKernelGGL(k_backward<THOI_SEL_MASK>, grid, dim3(64), lds, s, a);
+    if (sel->mode == THOI_SEL_RANGE) {
+        launch_bwd_engines(a, sel, s);
+        return hip_status(hipGetLastError());
+    }
+    // LIST / MASK: bucket the rows by order on the device (invalid rows go to the last bucket,
+    // contribute nothing and raise THOI_EINVAL_DATA in the status word)
+    char* base = static_cast<char*>(ws);
+    WsHeader* hdr = reinterpret_cast<WsHeader*>(base);
+    uint8_t* korder = reinterpret_cast<uint8_t*>(base + w.korder_off);
+    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(base + w.cnt_off);
+    int64_t* lbase = reinterpret_cast<int64_t*>(base + w.base_off);
+    int64_t* lblk0 = reinterpret_cast<int64_t*>(base + w.blk0_off);
+    unsigned long long* cursor = reinterpret_cast<unsigned long long*>(base + w.cursor_off);
+    int64_t* perm = reinterpret_cast<int64_t*>(base + w.perm_off);
+    a.perm = perm;
+    a.lcnt = reinterpret_cast<const int64_t*>(cnt);
+    a.lbase = lbase;
+    EvalArgs ea{};
+    ea.N = N;
+    ea.D = (int32_t)D;
+    ea.B = a.B;
+    ea.hdr = hdr;
+    ea.idx = sel->idx;
+    ea.kmax_list = sel->kmax_list;
+    ea.mask = sel->mask;
+    hipLaunchKernelGGL(k_ws_clear, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t*>(base), (int64_t)(kWsHeader / 4));
+    hipLaunchKernelGGL(k_ws_clear, dim3(1), dim3(256), 0, s, reinterpret_cast<uint32_t*>(cnt), (int64_t)kListOrders * 2);
+    const unsigned nb = (unsigned)((a.B + 255) / 256);
+    ClassMap cm{};
+    for (int k = 0; k < kListOrders; ++k) {
+        cm.wave[k] = k > a.lane_max ? 1 : 0;
+        cm.cls[k] = (int8_t)bwd_class_of(k <= kBwdLaneMax ? k : kBwdLaneMax);
+    }
+    if (sel->mode == THOI_SEL_LIST)
+        hipLaunchKernelGGL(k_list_classify<THOI_SEL_LIST>, dim3(nb), dim3(256), 0, s, ea, 1, a.B, korder, cnt);
+    else
+        hipLaunchKernelGGL(k_list_classify<THOI_SEL_MASK>, dim3(nb), dim3(256), 0, s, ea, 1, a.B, korder, cnt);
+    hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(64), 0, s, cnt, lbase, lblk0, cursor, cm, (int64_t)kBwdTile,
+                       (int64_t)1);
+    hipLaunchKernelGGL(k_list_scatter, dim3(nb), dim3(256), 0, s, a.B, korder, lbase, cursor, perm);
+    launch_bwd_engines(a, sel, s);
     return hip_status(hipGetLastError());
 }
 

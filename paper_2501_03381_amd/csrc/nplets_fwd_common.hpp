@@ -359,6 +359,113 @@ __global__ void k_ws_clear(uint32_t* p, int64_t n)
 }
 
 
+// grid ceil(B/256): order of every row (THOI_MAX_K + 1 = invalid) and per-order counts.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_list_classify(EvalArgs a, int reduce, int64_t Bn, uint8_t* __restrict__ korder,
+                                                       unsigned long long* __restrict__ cnt)
+{
+    __shared__ unsigned int h[kListOrders];
+    for (int i = threadIdx.x; i < kListOrders; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b < Bn) {
+        int k = 0;
+        bool ok = true;
+        if constexpr (MODE == THOI_SEL_LIST) {
+            const int32_t* row = a.idx + b * a.kmax_list;
+            int prev = -1;
+            for (int j = 0; j < a.kmax_list; ++j) {
+                const int v = row[j];
+                if (v < 0) {
+                    if (v != -1) ok = false;
+                    for (int jj = j + 1; jj < a.kmax_list; ++jj) ok = ok && (row[jj] == -1);
+                    break;
+                }
+                ok = ok && v > prev && v < a.N;
+                prev = v;
+                ++k;
+            }
+            ok = ok && k <= THOI_MAX_K;
+        } else {
+            const uint64_t m = a.mask[b];
+            k = __popcll(m);
+            ok = (a.N >= 64) || ((m >> a.N) == 0);
+        }
+        if (!ok) {
+            k = THOI_MAX_K + 1;
+            raise_status(a.hdr, THOI_EINVAL_DATA);
+            const int64_t plane = (int64_t)a.D * a.B;
+            for (int d = 0; d < a.D; ++d) {
+                const int64_t o = (int64_t)d * a.B + b;
+                if (!reduce && a.out) {
+                    for (int m = 0; m < 4 + a.write_H; ++m) {
+                        if (a.out_f32) static_cast<float*>(a.out)[m * plane + o] = __builtin_nanf("");
+                        else static_cast<double*>(a.out)[m * plane + o] = __builtin_nan("");
+                    }
+                }
+                if (a.flags) a.flags[o] = THOI_NPLET_NOT_PD;
+            }
+        }
+        korder[b] = (uint8_t)k;
+        atomicAdd(&h[k], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kListOrders; i += blockDim.x)
+        if (h[i]) atomicAdd(&cnt[i], (unsigned long long)h[i]);
+}
+
+struct ClassMap { int8_t cls[kListOrders]; int8_t wave[kListOrders]; };
+
+// 1 workgroup: per-order base in perm, and first workgroup of each order inside its launch.
+__global__ void k_list_scan(const unsigned long long* __restrict__ cnt, int64_t* __restrict__ base,
+                            int64_t* __restrict__ blk0, unsigned long long* __restrict__ cursor, ClassMap cm,
+                            int64_t per_lane_blk, int64_t per_wave_blk)
+{
+    if (threadIdx.x != 0) return;
+    int64_t b = 0;
+    int64_t ct[16] = {0};
+    int64_t wt = 0;
+    for (int k = 0; k < kListOrders; ++k) {
+        base[k] = b;
+        cursor[k] = 0;
+        const int64_t c = (int64_t)cnt[k];
+        b += c;
+        if (k > THOI_MAX_K) { blk0[k] = 0; continue; }
+        if (cm.wave[k]) {
+            blk0[k] = wt;
+            wt += (c + per_wave_blk - 1) / per_wave_blk;
+        } else {
+            const int cl = cm.cls[k];
+            blk0[k] = ct[cl];
+            ct[cl] += (c + per_lane_blk - 1) / per_lane_blk;
+        }
+    }
+}
+
+// grid ceil(B/256): perm[base[k] + slot] = b for every valid row.
+__global__ __launch_bounds__(256) void k_list_scatter(int64_t Bn, const uint8_t* __restrict__ korder,
+                                                      const int64_t* __restrict__ base,
+                                                      unsigned long long* __restrict__ cursor, int64_t* __restrict__ perm)
+{
+    __shared__ unsigned int h[kListOrders];
+    __shared__ unsigned long long start[kListOrders];
+    for (int i = threadIdx.x; i < kListOrders; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int k = -1;
+    unsigned int mine = 0;
+    if (b < Bn) {
+        k = korder[b];
+        if (k <= THOI_MAX_K) mine = atomicAdd(&h[k], 1u);
+        else k = -1;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kListOrders; i += blockDim.x)
+        start[i] = h[i] ? atomicAdd(&cursor[i], (unsigned long long)h[i]) : 0ull;
+    __syncthreads();
+    if (k >= 0) perm[base[k] + (int64_t)start[k] + mine] = b;
+}
+
 int64_t sel_B(const thoi_nplets* sel) { return sel->mode == THOI_SEL_RANGE ? sel->g_count : sel->B; }
 
 int sel_kmax(const thoi_nplets* sel, int N)

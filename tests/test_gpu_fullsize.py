@@ -159,7 +159,8 @@ def test_latent100_forward_and_adjoint(env):
 
 def test_latent100_adjoint_vs_finite_differences(env):
     """The method's differentiation check: the first 100 n-plets of the N=100 workload, each with
-    random weights on TC, DTC, Omega and S, adjoint (FP64 factorisation, FP32 accumulation) against
+    random weights on TC, DTC, Omega and S, adjoint (FP64 factorisation and inverse, FP32 quadratic
+    part and accumulation) against
     central differences h = 1e-6 of the oracle's literal measures.  Bound per n-plet: 1e-6 of its
     largest gradient entry (the FD error itself is below 6.1e-8 of it, FP32 rounding 6e-8)."""
     torch, api, B, synth, orc = env
