@@ -201,8 +201,8 @@ int bwd_class_of(int k)
     return c;
 }
 
-// Largest order of the lane engine for N variables: its staged FP64 matrix and accumulator tile
-// must fit in LDS (N <= 120); otherwise every order goes to the wave engine.
+// Largest order of the lane engine for N variables: its LDS (staged matrix when N <= 64, the
+// accumulator tile) must fit; otherwise every order goes to the wave engine.
 int bwd_lane_max(int N) { return bwd_lane_lds_bytes(N, kBwdLaneMax) <= kLdsLimit ? kBwdLaneMax : 0; }
 
 void bwd_lane_launch(int cls, const BwdArgs& a, const BwdTiles& t, int64_t ntiles, dim3 grid, size_t lds,
@@ -263,7 +263,7 @@ void launch_bwd_engines(BwdArgs& a, const thoi_nplets* sel, hipStream_t s)
                     p.pos0 = lo - gb;
                     p.cnt = hi - lo;
                     p.tile0 = ntiles[c];
-                    ntiles[c] += (p.cnt + kBwdTile - 1) / kBwdTile;
+                    ntiles[c] += (p.cnt + kBwdClassThreads[c] - 1) / kBwdClassThreads[c];
                     tabs[c].p[tabs[c].n++] = p;
                 } else {
                     if (!wave_start) { wave_s0 = lo - gb; wave_start = true; }
@@ -276,7 +276,8 @@ void launch_bwd_engines(BwdArgs& a, const thoi_nplets* sel, hipStream_t s)
     } else {
         const int kcap = sel_kmax(sel, N);
         for (int c = 0; c < kBwdNClasses; ++c) {
-            if (kBwdClasses[c].lo <= kcap && kBwdClasses[c].lo <= lane_max) ntiles[c] = (a.B + kBwdTile - 1) / kBwdTile;
+            if (kBwdClasses[c].lo <= kcap && kBwdClasses[c].lo <= lane_max)
+                ntiles[c] = (a.B + kBwdClassThreads[c] - 1) / kBwdClassThreads[c];
         }
         if (kcap > lane_max) { wave_cnt = a.B; wave_kmax = kcap; }
     }
@@ -402,8 +403,7 @@ thoi_status launch_backward(const double* Sigma, int64_t D, int32_t N, const tho
         hipLaunchKernelGGL(k_list_classify<THOI_SEL_LIST>, dim3(nb), dim3(256), 0, s, ea, 1, a.B, korder, cnt);
     else
         hipLaunchKernelGGL(k_list_classify<THOI_SEL_MASK>, dim3(nb), dim3(256), 0, s, ea, 1, a.B, korder, cnt);
-    hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(64), 0, s, cnt, lbase, lblk0, cursor, cm, (int64_t)kBwdTile,
-                       (int64_t)1);
+    hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(64), 0, s, cnt, lbase, lblk0, cursor, cm, (int64_t)1, (int64_t)1);
     hipLaunchKernelGGL(k_list_scatter, dim3(nb), dim3(256), 0, s, a.B, korder, lbase, cursor, perm);
     launch_bwd_engines(a, sel, s);
     return hip_status(hipGetLastError());

@@ -5,7 +5,6 @@
 
 namespace thoi {
 
-constexpr int kBwdTile = 256;          // n-plets (= threads) per lane-engine tile
 constexpr int kBwdMaxPieces = 24;      // RANGE: orders per lane-engine class
 
 // Lane-engine classes: orders [lo, hi] evaluated by one launch (one register footprint).
@@ -13,6 +12,11 @@ struct BwdClass { int lo, hi; };
 constexpr BwdClass kBwdClasses[] = {{0, 8}, {9, 12}, {13, 16}, {17, 20}};
 constexpr int kBwdNClasses = (int)(sizeof(kBwdClasses) / sizeof(BwdClass));
 constexpr int kBwdLaneMax = 20;
+// Threads per workgroup (= n-plets per tile) of each class.  Orders 0..8 use 64 VGPRs and run four
+// waves per SIMD in one workgroup; for the larger classes 1024- and 512-thread workgroups measured
+// slower than 256 at N = 100 (latent_100 adjoint: 200 / 170 us against 123 / 135 us per class).
+constexpr int kBwdClassThreads[] = {1024, 256, 256, 256};
+static_assert(sizeof(kBwdClassThreads) / sizeof(int) == kBwdNClasses, "one size per class");
 
 // RANGE: the n-plets of one order inside the call's range, and the first tile they occupy inside
 // their class's launch.
@@ -53,12 +57,17 @@ struct BwdArgs {
 
 __host__ __device__ inline size_t bwd_align16(size_t x) { return (x + 15) / 16 * 16; }
 
-// LDS of the lane engine: sR [N*N] f64 | sIsd [N] f64 | sLogd [N] f64 | sBin [N*kb] u64 (RANGE) |
-// sAcc [N (N+1) / 2] f32
+// The lane engine stages the FP64 correlation matrix in LDS when it is small (N <= 64: 32 KB);
+// larger matrices are read from global memory (they stay in L2), so that LDS does not cap the
+// workgroups per compute unit.
+__host__ __device__ inline bool bwd_stage_matrix(int N) { return N <= 64; }
+
+// LDS of the lane engine: sR [N*N] f64 (staged only) | sIsd [N] f64 | sLogd [N] f64 |
+// sBin [N*kb] u64 (RANGE) | sAcc [N (N+1) / 2] f32
 __host__ __device__ inline size_t bwd_lane_lds_bytes(int N, int kb)
 {
-    return bwd_align16(bwd_align16((size_t)N * N * 8) + (size_t)N * 16 + (size_t)N * kb * 8) +
-           bwd_align16((size_t)N * (N + 1) / 2 * 4);
+    const size_t r = bwd_stage_matrix(N) ? bwd_align16((size_t)N * N * 8) : 0;
+    return bwd_align16(r + (size_t)N * 16 + (size_t)N * kb * 8) + bwd_align16((size_t)N * (N + 1) / 2 * 4);
 }
 
 // Launch lane-engine class `cls` (nplets_bwd_lane_lo.hip: classes 0..2, nplets_bwd_lane_hi.hip:

@@ -12,13 +12,15 @@
 //   G_ij = c_T/2 delta_ij / d_i + u_i u_j [ (c_D - c_T)/2 Z_ij - c_D/2 (Z^2)_ij ],  u_i = t_i / sqrt(d_i),
 // one length-k dot product per pair i >= j.
 //
-// One lane owns one n-plet.  L = chol(R_S), W = L^-1 and P = W^T W overwrite one packed FP64
+// One lane owns one n-plet, gathered from the correlation matrix staged in LDS (N <= 64) or from
+// the covariance in global memory (larger N, scaled on the fly: LDS then holds only the
+// accumulator and does not cap the occupancy).  L = chol(R_S), W = L^-1 and P = W^T W overwrite one packed FP64
 // triangle in registers; Z, whose entries lie in [-1, 1], is then rounded to FP32 for the quadratic
 // part (that rounding, about 6e-8 of the diagonal terms of G, is the size of the FP32 accumulation
 // of the result), which halves the live state of the widest phase.  Contributions go with LDS
 // atomics into the packed lower triangle of an N x N FP32 tile per workgroup (n-plet indices
 // ascend, so c_i >= c_j); each workgroup flushes its tile once with float atomics.  Workgroups are
-// persistent over the tiles (kBwdTile n-plets of one order) of their class.
+// persistent over the tiles (one n-plet per thread, one order per tile) of their class.
 #pragma once
 
 #include <type_traits>
@@ -44,19 +46,31 @@ __device__ __forceinline__ void sfor(Fn&& fn)
 }
 
 template <int K>
-__device__ __forceinline__ void lane_adjoint(const int (&c)[K > 0 ? K : 1], const double* __restrict__ sR, int N,
-                                             const double* __restrict__ sIsd, double cT, double cD,
-                                             float* __restrict__ sAcc)
+__device__ __forceinline__ void lane_adjoint(const int (&c)[K > 0 ? K : 1], const double* __restrict__ sR,
+                                             const double* __restrict__ Sig, int N, const double* __restrict__ sIsd,
+                                             double cT, double cD, float* __restrict__ sAcc)
 {
     constexpr int NT = K * (K + 1) / 2;
     double a[NT > 0 ? NT : 1];
-    // gather R_S (strict lower triangle; unit diagonal) from the staged correlation matrix
+    // gather R_S (strict lower triangle; unit diagonal): from the staged correlation matrix, or
+    // from the covariance in global memory scaled by 1/sqrt(Sigma_ii Sigma_jj)
+    if (bwd_stage_matrix(N)) {
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-        const double* row = sR + c[i] * N;
+        for (int i = 0; i < K; ++i) {
+            const double* row = sR + c[i] * N;
 #pragma unroll
-        for (int j = 0; j < i; ++j) a[tri(i, j)] = row[c[j]];
-        a[tri(i, i)] = 1.0;
+            for (int j = 0; j < i; ++j) a[tri(i, j)] = row[c[j]];
+            a[tri(i, i)] = 1.0;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int ri = c[i] * N;
+            const double si = sIsd[c[i]];
+#pragma unroll
+            for (int j = 0; j < i; ++j) a[tri(i, j)] = Sig[ri + c[j]] * si * sIsd[c[j]];
+            a[tri(i, i)] = 1.0;
+        }
     }
     // Cholesky R_S = L L^T; the diagonal slot keeps 1 / L_jj
     bool ok = true;
@@ -154,7 +168,7 @@ __device__ __forceinline__ bool bwd_lane_weights(const BwdArgs& a, int d, int64_
 
 template <int K>
 __device__ __forceinline__ void bwd_lane_task(const BwdArgs& a, int d, const double* __restrict__ sR,
-                                              const double* __restrict__ sIsd, const uint64_t* __restrict__ sBin,
+                                              const double* __restrict__ Sig, const double* __restrict__ sIsd, const uint64_t* __restrict__ sBin,
                                               int kb, float* __restrict__ sAcc, int64_t first, int64_t pos0,
                                               int64_t local)
 {
@@ -177,43 +191,56 @@ __device__ __forceinline__ void bwd_lane_task(const BwdArgs& a, int d, const dou
     }
     double cT, cD;
     if (!bwd_lane_weights(a, d, pos, cT, cD)) return;
-    lane_adjoint<K>(c, sR, a.N, sIsd, cT, cD, sAcc);
+    lane_adjoint<K>(c, sR, Sig, a.N, sIsd, cT, cD, sAcc);
 }
 
 template <int K, int KHI>
-__device__ __forceinline__ void bwd_lane_dispatch(int k, const BwdArgs& a, int d, const double* sR, const double* sIsd,
-                                                  const uint64_t* sBin, int kb, float* sAcc, int64_t first,
-                                                  int64_t pos0, int64_t local)
+__device__ __forceinline__ void bwd_lane_dispatch(int k, const BwdArgs& a, int d, const double* sR, const double* Sig,
+                                                  const double* sIsd, const uint64_t* sBin, int kb, float* sAcc,
+                                                  int64_t first, int64_t pos0, int64_t local)
 {
-    if (k == K) bwd_lane_task<K>(a, d, sR, sIsd, sBin, kb, sAcc, first, pos0, local);
-    else if constexpr (K < KHI) bwd_lane_dispatch<K + 1, KHI>(k, a, d, sR, sIsd, sBin, kb, sAcc, first, pos0, local);
+    if (k == K) bwd_lane_task<K>(a, d, sR, Sig, sIsd, sBin, kb, sAcc, first, pos0, local);
+    else if constexpr (K < KHI)
+        bwd_lane_dispatch<K + 1, KHI>(k, a, d, sR, Sig, sIsd, sBin, kb, sAcc, first, pos0, local);
 }
 
-// grid (workgroups, D), block kBwdTile; workgroup x walks tiles x, x + gridDim.x, ... of its class.
+// grid (workgroups, D), block BS; workgroup x walks tiles (BS n-plets of one order) x, x + gridDim.x,
+// ... of its class.
 // RANGE: tab.p[i].tile0 is the piece's first tile and ntiles_range the class's tile count;
 // LIST / MASK: tiles follow the per-order buckets of orders KLO..KHI.
-template <int KLO, int KHI>
-__global__ __launch_bounds__(kBwdTile) void k_bwd_lane(BwdArgs a, BwdTiles tab, int64_t ntiles_range)
+template <int KLO, int KHI, int BS>
+__global__ __launch_bounds__(BS) void k_bwd_lane(BwdArgs a, BwdTiles tab, int64_t ntiles_range)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = a.N;
     const int d = blockIdx.y;
     const bool range = a.mode == THOI_SEL_RANGE;
     const int kb = range ? KHI : 0;
+    const bool staged = bwd_stage_matrix(N);
     double* sR = reinterpret_cast<double*>(smem);
-    const size_t off = bwd_align16((size_t)N * N * 8);
+    const size_t off = staged ? bwd_align16((size_t)N * N * 8) : 0;
     double* sIsd = reinterpret_cast<double*>(smem + off);
     double* sLogd = sIsd + N;
     uint64_t* sBin = reinterpret_cast<uint64_t*>(sLogd + N);
     float* sAcc = reinterpret_cast<float*>(smem + bwd_align16(off + (size_t)N * 16 + (size_t)N * kb * 8));
     const int NTN = N * (N + 1) / 2;
     for (int e = threadIdx.x; e < NTN; e += blockDim.x) sAcc[e] = 0.0f;
-    stage_corr<double>(a.Sigma + (int64_t)d * N * N, N, sR, sIsd, sLogd, range ? sBin : nullptr, kb);
+    const double* Sig = a.Sigma + (int64_t)d * N * N;
+    if (staged) {
+        stage_corr<double>(Sig, N, sR, sIsd, sLogd, range ? sBin : nullptr, kb);
+    } else {
+        for (int j = threadIdx.x; j < N; j += blockDim.x) {
+            const double dj = Sig[(int64_t)j * N + j];
+            sIsd[j] = dj > 0.0 ? 1.0 / sqrt(dj) : __builtin_nan("");
+        }
+        if (range) stage_binomials(N, kb, sBin);
+        __syncthreads();
+    }
 
     int64_t ntiles = ntiles_range;
     if (!range) {
         ntiles = 0;
-        for (int kk = KLO; kk <= KHI; ++kk) ntiles += (a.lcnt[kk] + kBwdTile - 1) / kBwdTile;
+        for (int kk = KLO; kk <= KHI; ++kk) ntiles += (a.lcnt[kk] + BS - 1) / BS;
     }
     bool any = false;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -221,25 +248,25 @@ __global__ __launch_bounds__(kBwdTile) void k_bwd_lane(BwdArgs a, BwdTiles tab, 
         int64_t first = 0, pos0 = 0, cnt = 0, tb = 0;
         if (range) {
             for (int p = 0; p < tab.n; ++p) {
-                const int64_t nt = (tab.p[p].cnt + kBwdTile - 1) / kBwdTile;
+                const int64_t nt = (tab.p[p].cnt + BS - 1) / BS;
                 if (t >= tab.p[p].tile0 && t < tab.p[p].tile0 + nt) {
                     k = tab.p[p].k; first = tab.p[p].first; pos0 = tab.p[p].pos0; cnt = tab.p[p].cnt;
-                    tb = (t - tab.p[p].tile0) * kBwdTile;
+                    tb = (t - tab.p[p].tile0) * BS;
                 }
             }
         } else {
             int64_t t0 = 0;
             for (int kk = KLO; kk <= KHI; ++kk) {
                 const int64_t c = a.lcnt[kk];
-                const int64_t nt = (c + kBwdTile - 1) / kBwdTile;
-                if (t >= t0 && t < t0 + nt) { k = kk; first = a.lbase[kk]; cnt = c; tb = (t - t0) * kBwdTile; }
+                const int64_t nt = (c + BS - 1) / BS;
+                if (t >= t0 && t < t0 + nt) { k = kk; first = a.lbase[kk]; cnt = c; tb = (t - t0) * BS; }
                 t0 += nt;
             }
         }
         if (k < 0) continue;   // uniform
         any = true;
         const int64_t local = tb + threadIdx.x;
-        if (local < cnt) bwd_lane_dispatch<KLO, KHI>(k, a, d, sR, sIsd, sBin, kb, sAcc, first, pos0, local);
+        if (local < cnt) bwd_lane_dispatch<KLO, KHI>(k, a, d, sR, Sig, sIsd, sBin, kb, sAcc, first, pos0, local);
     }
     __syncthreads();
     if (!any) return;   // uniform
@@ -251,18 +278,18 @@ __global__ __launch_bounds__(kBwdTile) void k_bwd_lane(BwdArgs a, BwdTiles tab, 
     }
 }
 
-template <int KLO, int KHI>
+template <int KLO, int KHI, int BS>
 void bwd_lane_launch_one(const BwdArgs& a, const BwdTiles& t, int64_t ntiles, dim3 grid, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_bwd_lane<KLO, KHI>), grid, dim3(kBwdTile), lds, s, a, t, ntiles);
+    hipLaunchKernelGGL((k_bwd_lane<KLO, KHI, BS>), grid, dim3(BS), lds, s, a, t, ntiles);
 }
 
-template <int KLO, int KHI>
+template <int KLO, int KHI, int BS>
 int bwd_lane_blocks_one(size_t lds)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(k_bwd_lane<KLO, KHI>),
-                                                     kBwdTile, lds) != hipSuccess || n < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(k_bwd_lane<KLO, KHI, BS>),
+                                                     BS, lds) != hipSuccess || n < 1)
         n = 1;
     return n;
 }

@@ -8,13 +8,13 @@ void bwd_lane_launch_hi(int cls, const BwdArgs& a, const BwdTiles& t, int64_t nt
 {
     static_assert(kBwdClasses[3].lo == 17 && kBwdClasses[3].hi == 20 && kBwdLaneMax == 20, "class table");
     (void)cls;
-    bwd_lane_launch_one<17, 20>(a, t, ntiles, grid, lds, s);
+    bwd_lane_launch_one<17, 20, kBwdClassThreads[3]>(a, t, ntiles, grid, lds, s);
 }
 
 int bwd_lane_blocks_per_cu_hi(int cls, size_t lds)
 {
     (void)cls;
-    return bwd_lane_blocks_one<17, 20>(lds);
+    return bwd_lane_blocks_one<17, 20, kBwdClassThreads[3]>(lds);
 }
 
 }  // namespace thoi

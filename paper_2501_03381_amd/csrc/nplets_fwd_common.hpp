@@ -372,18 +372,26 @@ __global__ __launch_bounds__(256) void k_list_classify(EvalArgs a, int reduce, i
         int k = 0;
         bool ok = true;
         if constexpr (MODE == THOI_SEL_LIST) {
+            // the row's entries are read eight at a time, all loads of a batch in flight together:
+            // strictly ascending ids in [0, N), then only -1 padding
             const int32_t* row = a.idx + b * a.kmax_list;
             int prev = -1;
-            for (int j = 0; j < a.kmax_list; ++j) {
-                const int v = row[j];
-                if (v < 0) {
-                    if (v != -1) ok = false;
-                    for (int jj = j + 1; jj < a.kmax_list; ++jj) ok = ok && (row[jj] == -1);
-                    break;
+            bool ended = false;
+            for (int j0 = 0; j0 < a.kmax_list; j0 += 8) {
+                int v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = j0 + u < a.kmax_list ? row[j0 + u] : -1;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    if (ended || v[u] < 0) {
+                        ok = ok && v[u] == -1;
+                        ended = true;
+                    } else {
+                        ok = ok && v[u] > prev && v[u] < a.N;
+                        prev = v[u];
+                        ++k;
+                    }
                 }
-                ok = ok && v > prev && v < a.N;
-                prev = v;
-                ++k;
             }
             ok = ok && k <= THOI_MAX_K;
         } else {
@@ -421,24 +429,45 @@ __global__ void k_list_scan(const unsigned long long* __restrict__ cnt, int64_t*
                             int64_t* __restrict__ blk0, unsigned long long* __restrict__ cursor, ClassMap cm,
                             int64_t per_lane_blk, int64_t per_wave_blk)
 {
-    if (threadIdx.x != 0) return;
-    int64_t b = 0;
-    int64_t ct[16] = {0};
-    int64_t wt = 0;
-    for (int k = 0; k < kListOrders; ++k) {
-        base[k] = b;
+    // One thread per order loads its count and class, and divides the count into workgroups (a
+    // 64-bit division is a long instruction sequence); one thread then scans in LDS only (byte reads
+    // of the class map from the kernel arguments, or global stores, in that serial loop made every
+    // iteration wait for memory); all threads write the results.
+    __shared__ int64_t c[kListOrders], nb[kListOrders], sb[kListOrders], sk[kListOrders];
+    __shared__ int64_t ct[16];
+    __shared__ int8_t wv[kListOrders], cl[kListOrders];
+    for (int k = threadIdx.x; k < kListOrders; k += blockDim.x) {
+        const int64_t ck = (int64_t)cnt[k];
+        const bool w = cm.wave[k] != 0;
+        c[k] = ck;
+        wv[k] = w ? 1 : 0;
+        cl[k] = cm.cls[k];
+        const int64_t per = w ? per_wave_blk : per_lane_blk;
+        nb[k] = k > THOI_MAX_K ? 0 : (ck + per - 1) / per;
         cursor[k] = 0;
-        const int64_t c = (int64_t)cnt[k];
-        b += c;
-        if (k > THOI_MAX_K) { blk0[k] = 0; continue; }
-        if (cm.wave[k]) {
-            blk0[k] = wt;
-            wt += (c + per_wave_blk - 1) / per_wave_blk;
-        } else {
-            const int cl = cm.cls[k];
-            blk0[k] = ct[cl];
-            ct[cl] += (c + per_lane_blk - 1) / per_lane_blk;
+    }
+    for (int k = threadIdx.x; k < 16; k += blockDim.x) ct[k] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t b = 0;
+        int64_t wt = 0;
+        for (int k = 0; k < kListOrders; ++k) {
+            sb[k] = b;
+            b += c[k];
+            if (k > THOI_MAX_K) { sk[k] = 0; continue; }
+            if (wv[k]) {
+                sk[k] = wt;
+                wt += nb[k];
+            } else {
+                sk[k] = ct[cl[k]];
+                ct[cl[k]] += nb[k];
+            }
         }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kListOrders; k += blockDim.x) {
+        base[k] = sb[k];
+        blk0[k] = sk[k];
     }
 }
 
