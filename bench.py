@@ -194,6 +194,36 @@ def kernel_ms(torch, fn, reps=50):
     return best
 
 
+def prefix_flops(N: int, k: int, L: int) -> int:
+    """The prefix engine's own algorithmic flops for all C(N, k) n-plets of order k at L tails per
+    lane, from its schedule: per lane, the Cholesky, inverse and column norms of the (k-S)-prefix
+    and the first borderings of the interior tail levels; per n-plet, the last bordering (l = W v,
+    s, w = W^T l, the k-1 updated inverse diagonal entries); per step to the next tail, the
+    re-borderings of the interior levels from the first changed tail position on.  A bordering
+    of a factor of size R costs R(R+1) + 2R multiply-adds."""
+    S = 3 if k >= 4 else 2
+    M = k - S
+    pre = (M ** 3 - M) // 3 + M * (M + 1) // 2
+    bord = lambda R: R * (R + 1) + 2 * R
+    total = 0
+    for q in range(M - 1, N - S):
+        npref = math.comb(q, M - 1)
+        nt = N - 1 - q
+        tails = list(__import__("itertools").combinations(range(nt), S))
+        fma = 0
+        for c0 in range(0, len(tails), L):
+            fma += pre + sum(bord(M + lv - 1) for lv in range(1, S))
+            chunk = tails[c0:c0 + L]
+            for i, t in enumerate(chunk):
+                fma += bord(k - 1) + (k - 1)
+                if i + 1 < len(chunk):
+                    nxt = chunk[i + 1]
+                    piv = next(j for j in range(S) if t[j] != nxt[j])
+                    fma += sum(bord(M + lv - 1) for lv in range(piv + 1, S))
+        total += npref * fma
+    return 2 * total
+
+
 def bench_ar1_30(torch, np, api, B, synth, dev, args):
     """N=30, T=1200 AR(1) mixture: all 1,073,741,358 n-plets of orders 3..30 with a streaming
     per-order top-100 / bottom-100 Omega and a 256-bin Omega histogram (no per-n-plet output).
@@ -228,6 +258,29 @@ def bench_ar1_30(torch, np, api, B, synth, dev, args):
         tv, tg, h = st.result()
         res[prec] = {"seconds": dt, "nplets_per_s": total / dt, "hist_total": int(h.sum()),
                      "max_omega": float(np.nanmax(tv[0, :, 0, 0])), "min_omega": float(np.nanmin(tv[0, :, 1, 0]))}
+    # the prefix-sharing engine against the factorisation engine on orders 7..12 (where the library
+    # chooses it), with each engine's own algorithmic flops
+    n712 = B.thoi_count(N, 7, 12)
+    eng = {}
+    for prec in ("fp32_refine", "fp64"):
+        for engine in ("factor", "prefix"):
+            best = float("inf")
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                api.nplets_reduce(Sigma, orders=(7, 12), topk=100, hist_bins=256, hist_range=lohi[:13],
+                                  precision=prec, engine=engine, check=False)
+                torch.cuda.synchronize()
+                best = min(best, time.perf_counter() - t0)
+            if engine == "prefix":
+                fl = sum(prefix_flops(N, k, max(1, min(16, 1 << int(math.log2(max(1.0, math.comb(N, k) / 262144.0))))))
+                         for k in range(7, 13))
+            else:
+                fl = sum(math.comb(N, k) * flops(k) for k in range(7, 13))
+            ach = fl / best / 1e12
+            eng[f"{prec} {engine}"] = {"seconds": best, "nplets_per_s": n712 / best, "flops": fl,
+                                       "tflops": round(ach, 3), "frac_of_78.6": round(ach / 78.6, 4)}
+    res["orders_7_12_engines"] = eng
     return {"workload": "ar1_30: N=30, T=1200, seed 2, all orders 3..30 (1,073,741,358 n-plets), streaming "
                         "top-100/bottom-100 + 256-bin histogram per order", "metric": "n-plets/s",
             "value": res["fp32_refine"]["nplets_per_s"], "unit": "n-plets/s", "nplets": total, "detail": res}

@@ -129,7 +129,24 @@ typedef struct {
     const thoi_reduce* reduce;   /* host; NULL = write the full output planes                    */
     int32_t seg_tiles;           /* tuning: tiles of 256 n-plets per workgroup; 0 = library choice */
     int32_t grid_blocks;         /* tuning: workgroups of a persistent launch; 0 = library choice  */
+    int32_t engine;              /* THOI_ENGINE_*: how whole orders of a RANGE selection are       */
+                                 /* factored (same results to rounding; other selections ignore it) */
 } thoi_eval_opts;
+
+/*
+ * Engines for the orders of a RANGE selection that the call covers completely:
+ *  THOI_ENGINE_FACTOR: one Cholesky factorisation per n-plet (every order).
+ *  THOI_ENGINE_PREFIX: prefix sharing (Supplementary, "The combinatorial explosion": the cost is
+ *    one factorisation per n-plet of every order).  In lexicographic order the n-plets that share
+ *    their first k - 2 variables are consecutive; each prefix is factored once and its factor is
+ *    bordered with the remaining two variables, x1 then x2 (the first bordering shared by all
+ *    pairs starting with x1): about 2 (k-1)^2 multiply-adds per n-plet instead of 2 (k^3-k)/3 +
+ *    k(k+1) flops.  Orders 3..16 in FP32, 3..12 in FP64; others use the factorisation engine.
+ *  THOI_ENGINE_AUTO (0): the library's choice: the prefix engine for orders 7..12 of an FP64
+ *    streaming reduction with at least 4 tails per lane (C(N, k) D >= 2^20), where it measured
+ *    faster; the factorisation engine otherwise.
+ */
+enum { THOI_ENGINE_AUTO = 0, THOI_ENGINE_FACTOR = 1, THOI_ENGINE_PREFIX = 2 };
 
 /*
  * Gaussian-copula transform (Supplementary, Eq. gaussian_copula_covariance_estimator):

@@ -116,12 +116,18 @@ def _n_out(sel: B.ThoiNplets) -> int:
     return sel.g_count if sel.mode == B.THOI_SEL_RANGE else sel.B
 
 
+_ENGINE = {"auto": B.THOI_ENGINE_AUTO, "factor": B.THOI_ENGINE_FACTOR, "prefix": B.THOI_ENGINE_PREFIX}
+
+
 def make_opts(precision: str = "fp32_refine", out_dtype: torch.dtype = torch.float32, vif_tau: float = 1e3,
               bias_correct: bool = False, T: int = 0, write_entropy: bool = False, seg_tiles: int = 0,
-              grid_blocks: int = 0) -> B.ThoiEvalOpts:
+              grid_blocks: int = 0, engine: str = "auto") -> B.ThoiEvalOpts:
+    """Evaluation options; engine: "auto", "factor" (one factorisation per n-plet) or "prefix"
+    (prefix sharing for the whole orders of a RANGE selection)."""
     return B.ThoiEvalOpts(precision=_PREC[precision], out_dtype=_DT[out_dtype], vif_tau=float(vif_tau),
                           bias_correct=int(bool(bias_correct)), T=int(T), write_entropy=int(bool(write_entropy)),
-                          reduce=None, seg_tiles=int(seg_tiles), grid_blocks=int(grid_blocks))
+                          reduce=None, seg_tiles=int(seg_tiles), grid_blocks=int(grid_blocks),
+                          engine=_ENGINE[engine])
 
 
 # ------------------------------------------------------------------------------------------------ evaluation
@@ -164,7 +170,7 @@ def nplets_measures(Sigma: torch.Tensor, *, orders: tuple[int, int] | None = Non
                     g_range: tuple[int, int] | None = None, nplets: torch.Tensor | None = None,
                     masks: torch.Tensor | None = None, precision: str = "fp32_refine",
                     out_dtype: torch.dtype = torch.float32, vif_tau: float = 1e3, bias_correct: bool = False,
-                    T: int = 0, write_entropy: bool = False, check: bool = True):
+                    T: int = 0, write_entropy: bool = False, check: bool = True, engine: str = "auto"):
     """(TC, DTC, Omega, S[, H]) of every selected n-plet for every covariance matrix.
 
     Sigma: float64 [N, N] or [D, N, N] on the device.  Select with exactly one of
@@ -191,7 +197,7 @@ def nplets_measures(Sigma: torch.Tensor, *, orders: tuple[int, int] | None = Non
     else:
         masks = masks.contiguous()
         sel, keep = mask_selection(masks), (masks,)
-    opts = make_opts(precision, out_dtype, vif_tau, bias_correct, T, write_entropy)
+    opts = make_opts(precision, out_dtype, vif_tau, bias_correct, T, write_entropy, engine=engine)
     ev = Evaluator(D, N, sel, opts, S.device, out_dtype, keep)
     out, flags = ev(S)
     if check:
@@ -293,7 +299,7 @@ class ReduceState:
 def nplets_reduce(Sigma: torch.Tensor, *, orders=None, g_range=None, nplets=None, masks=None, topk: int = 100,
                   hist_bins: int = 256, hist_range=(-10.0, 10.0), precision: str = "fp32_refine",
                   vif_tau: float = 1e3, bias_correct: bool = False, T: int = 0, state: ReduceState | None = None,
-                  flags: torch.Tensor | None = None, check: bool = True) -> ReduceState:
+                  flags: torch.Tensor | None = None, check: bool = True, engine: str = "auto") -> ReduceState:
     """Streaming reduction of Omega over the selected n-plets (no per-n-plet output).
 
     hist_range: (lo, hi) for every order, or an array [kmax+1, 2].  Pass `state` from an
@@ -313,7 +319,7 @@ def nplets_reduce(Sigma: torch.Tensor, *, orders=None, g_range=None, nplets=None
         state = ReduceState(D, kmax, topk, hist_bins, hist_range, S.device)
     if (state.D, state.kmax) != (D, kmax):
         raise ValueError("state does not match this selection")
-    opts = make_opts(precision, torch.float32, vif_tau, bias_correct, T, False)
+    opts = make_opts(precision, torch.float32, vif_tau, bias_correct, T, False, engine=engine)
     opts.reduce = ctypes.pointer(state.struct)
     nb = B.thoi_workspace_bytes(B.THOI_WS_EVAL, D, 0, N, sel, opts)
     ws = _workspace(nb, S.device)

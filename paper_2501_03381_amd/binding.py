@@ -25,6 +25,7 @@ THOI_SEL_RANGE, THOI_SEL_LIST, THOI_SEL_MASK = 0, 1, 2
 THOI_NPLET_REFINED, THOI_NPLET_NOT_PD = 1, 2
 THOI_WS_COPULIZE, THOI_WS_COV, THOI_WS_EVAL, THOI_WS_BACKWARD = 0, 1, 2, 3
 THOI_OBJ_MEAN, THOI_OBJ_PAIRED_EFFECT = 0, 1
+THOI_ENGINE_AUTO, THOI_ENGINE_FACTOR, THOI_ENGINE_PREFIX = 0, 1, 2
 THOI_MAX_N_RANGE = 62
 THOI_MAX_N = 128
 THOI_MAX_K = 64
@@ -75,6 +76,7 @@ class ThoiEvalOpts(ctypes.Structure):
         ("reduce", ctypes.POINTER(ThoiReduce)),
         ("seg_tiles", ctypes.c_int32),
         ("grid_blocks", ctypes.c_int32),
+        ("engine", ctypes.c_int32),
     ]
 
 

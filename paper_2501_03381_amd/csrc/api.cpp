@@ -163,6 +163,7 @@ thoi_status thoi::check_eval(const double* Sigma, int64_t D, int32_t N, const th
     }
     if (opts->write_entropy != 0 && opts->write_entropy != 1) return THOI_EINVAL;
     if (opts->seg_tiles < 0 || opts->grid_blocks < 0) return THOI_EINVAL;
+    if (opts->engine < THOI_ENGINE_AUTO || opts->engine > THOI_ENGINE_PREFIX) return THOI_EINVAL;
     if (opts->seg_tiles > 4096) return THOI_EUNSUPPORTED;
     if (forward) {
         if (opts->reduce) {

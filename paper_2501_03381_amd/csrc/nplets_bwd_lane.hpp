@@ -23,8 +23,6 @@
 // persistent over the tiles (one n-plet per thread, one order per tile) of their class.
 #pragma once
 
-#include <type_traits>
-
 #include "nplets_bwd.hpp"
 #include "nplets_common.hpp"
 
@@ -32,18 +30,6 @@ namespace thoi {
 namespace {
 
 __device__ __forceinline__ int ptri(int i, int j) { return i * (i + 1) / 2 + j; }   // i >= j
-
-// Compile-time loop: fn(integral_constant<int, B>), ..., fn(integral_constant<int, E - 1>).  Used
-// for the nests whose inner trip counts depend on the outer index: #pragma unroll does not always
-// unroll them fully, which would leave the triangle dynamically indexed, i.e. in scratch memory.
-template <int B, int E, typename Fn>
-__device__ __forceinline__ void sfor(Fn&& fn)
-{
-    if constexpr (B < E) {
-        fn(std::integral_constant<int, B>{});
-        sfor<B + 1, E>(fn);
-    }
-}
 
 template <int K>
 __device__ __forceinline__ void lane_adjoint(const int (&c)[K > 0 ? K : 1], const double* __restrict__ sR,

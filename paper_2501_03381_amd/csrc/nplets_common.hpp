@@ -13,6 +13,8 @@
 //   TC = -ld/2,  DTC = (ld + sum_j log a_j)/2,  Omega = TC - DTC,  S = TC + DTC.
 #pragma once
 
+#include <type_traits>
+
 #include "thoi_internal.hpp"
 
 namespace thoi {
@@ -36,6 +38,18 @@ template <> struct Num<double> {
     static __device__ __forceinline__ int expo(double x) { return __builtin_amdgcn_frexp_exp(x); }
     static __device__ __forceinline__ double log2m(double m) { return log2(m); }
 };
+
+// Compile-time loop: fn(integral_constant<int, B>), ..., fn(integral_constant<int, E - 1>).  Used
+// for the nests whose inner trip counts depend on the outer index: #pragma unroll does not always
+// unroll them fully, which would leave the triangle dynamically indexed, i.e. in scratch memory.
+template <int B, int E, typename Fn>
+__device__ __forceinline__ void sfor(Fn&& fn)
+{
+    if constexpr (B < E) {
+        fn(std::integral_constant<int, B>{});
+        sfor<B + 1, E>(fn);
+    }
+}
 
 // Running product kept as mantissa * 2^exponent, so products of up to 64 pivots or VIFs never
 // leave the normal range.

@@ -14,6 +14,7 @@
 // a follow-up FP64 kernel re-evaluates exactly those and overwrites their results.
 // Results go either to the output planes or to the streaming reducer (reduce_common.hpp).
 #include "nplets_fwd_common.hpp"
+#include "nplets_prefix.hpp"
 
 namespace thoi {
 
@@ -277,17 +278,45 @@ struct Plan {
     int seg_tiles, wave_tile;
     int64_t seg_cap;
     bool serial;     // every launch on the caller's stream (no side streams)
+    int npcls;       // prefix engine: classes, their order tables and workgroups
+    PfxTable ptabs[4];
+    int64_t pnblk[4];
 };
 
-// Grids are kept well below the dispatch limit of 2^32 work-items along x: a class grid by
-// growing the tiles per workgroup, the wave grid by growing the n-plets per workgroup (both
-// engines loop over their share, so any tile count is valid).
-constexpr int64_t kMaxGridItems = int64_t(1) << 30;
+// Prefix engine for order k of this precision: the class index, or -1.
+int pfx_class_of(bool f64, int k)
+{
+    const PfxClass* cls = f64 ? kPfxF64Classes : kPfxF32Classes;
+    const int n = f64 ? (int)(sizeof(kPfxF64Classes) / sizeof(PfxClass)) : (int)(sizeof(kPfxF32Classes) / sizeof(PfxClass));
+    for (int c = 0; c < n; ++c)
+        if (k >= cls[c].lo && k <= cls[c].hi) return c;
+    return -1;
+}
+
+// Whether a whole order k of a RANGE call goes to the prefix engine.  The library's choice
+// (THOI_ENGINE_AUTO) follows measurements of both engines on the N = 30 reduction, orders 7..12 in
+// one call: in FP64 the prefix engine took 22.4 ms against 30.2 ms; in FP32 13.0 ms against
+// 11.9 ms (the factorisation engine's concurrent class launches keep the GPU fuller).  Orders up
+// to 6 have too few prefixes per workgroup, and in output mode each lane's outputs are consecutive
+// but the lanes' are far apart, so the stores do not coalesce.
+bool use_prefix(int engine, bool reduce, bool f64, int N, int k, int64_t D)
+{
+    if (engine == THOI_ENGINE_PREFIX) return true;
+    if (engine != THOI_ENGINE_AUTO) return false;
+    return f64 && reduce && k >= 7 && k <= 12 && pfx_tails(N, k, D) >= 4;
+}
 
 template <typename F>
-Plan make_plan(int N, const thoi_nplets* sel, bool reduce, int precision, int seg_tiles_hint)
+Plan make_plan(int N, int64_t D, const thoi_nplets* sel, bool reduce, int precision, int seg_tiles_hint, int engine)
 {
     Plan P{};
+    const bool f64 = sizeof(F) == 8;
+    P.npcls = f64 ? (int)(sizeof(kPfxF64Classes) / sizeof(PfxClass)) : (int)(sizeof(kPfxF32Classes) / sizeof(PfxClass));
+    // an order goes to the prefix engine when the call covers it completely
+    auto prefix_order = [&](int k, int64_t lo, int64_t hi, int64_t g, int64_t ck) {
+        return sel->mode == THOI_SEL_RANGE && use_prefix(engine, reduce, f64, N, k, D) && pfx_class_of(f64, k) >= 0 &&
+               lo == g && hi == g + ck;
+    };
     const KClass* cls = classes_for<F>(P.ncls);
     const int lane_max = lane_max_for(precision);
     const int64_t Bn = sel_B(sel);
@@ -312,7 +341,7 @@ Plan make_plan(int N, const thoi_nplets* sel, bool reduce, int precision, int se
         for (int k = sel->kmin; k <= sel->kmax; ++k) {
             const int64_t ck = (int64_t)binom_u64(N, k);
             const int64_t lo = gb > g ? gb : g, hi = ge < g + ck ? ge : g + ck;
-            if (hi > lo) {
+            if (hi > lo && !prefix_order(k, lo, hi, g, ck)) {
                 if (k <= lane_max) cls_cnt[class_of<F>(k)] += hi - lo;
                 else wave_cnt += hi - lo;
             }
@@ -343,7 +372,18 @@ Plan make_plan(int N, const thoi_nplets* sel, bool reduce, int precision, int se
         for (int k = sel->kmin; k <= sel->kmax; ++k) {
             const int64_t ck = (int64_t)binom_u64(N, k);
             const int64_t lo = gb > g ? gb : g, hi = ge < g + ck ? ge : g + ck;
-            if (hi > lo) {
+            if (hi > lo && prefix_order(k, lo, hi, g, ck)) {
+                const int c = pfx_class_of(f64, k);
+                PfxPiece pp{};
+                pp.k = k;
+                pp.pos0 = lo - gb;
+                pp.L = pfx_tails(N, k, D);
+                pp.nblk = pfx_blocks(N, k, pp.L);
+                pp.nphys = pp.nblk < kPfxMaxGroups ? pp.nblk : kPfxMaxGroups;
+                pp.blk0 = P.pnblk[c];
+                P.pnblk[c] += pp.nphys;
+                P.ptabs[c].p[P.ptabs[c].n++] = pp;
+            } else if (hi > lo) {
                 Piece p{};
                 p.k = k;
                 p.first = lo - g;
@@ -374,6 +414,7 @@ Plan make_plan(int N, const thoi_nplets* sel, bool reduce, int precision, int se
     }
     P.seg_cap = P.wblk;
     for (int c = 0; c < P.ncls; ++c) P.seg_cap += P.nblk[c];
+    for (int c = 0; c < P.npcls; ++c) P.seg_cap += P.pnblk[c];
     return P;
 }
 
@@ -406,8 +447,8 @@ EvalWs eval_layout(int64_t D, int32_t N, const thoi_nplets* sel, const thoi_eval
     }
     if (reduce && opts->reduce->topk > 0) {
         const int K = opts->reduce->topk;
-        const Plan P = opts->precision == THOI_FP64 ? make_plan<double>(N, sel, true, opts->precision, opts->seg_tiles)
-                                                    : make_plan<float>(N, sel, true, opts->precision, opts->seg_tiles);
+        const Plan P = opts->precision == THOI_FP64 ? make_plan<double>(N, D, sel, true, opts->precision, opts->seg_tiles, opts->engine)
+                                                    : make_plan<float>(N, D, sel, true, opts->precision, opts->seg_tiles, opts->engine);
         const int64_t segs = P.seg_cap * D;
         w.seg_cap = (uint32_t)(segs > 0 ? segs : 1);
         w.seg_key_off = off; off = align_up(off + (size_t)w.seg_cap * 2 * K * 8, 256);
@@ -468,8 +509,15 @@ void launch_engines(EvalArgs& a, const Plan& P, const RedArgs& red, hipStream_t 
     // the class launches are independent: fan them out over side streams
     int nl = P.wblk ? 1 : 0;
     for (int c = 0; c < ncls; ++c) nl += P.nblk[c] != 0;
+    for (int c = 0; c < P.npcls; ++c) nl += P.pnblk[c] != 0;
     FanScope fan(s, P.serial ? 1 : nl);
     int b = 0;
+    if constexpr (MODE == THOI_SEL_RANGE) {
+        for (int c = P.npcls - 1; c >= 0; --c) {      // the longest lanes first
+            if (P.pnblk[c] == 0) continue;
+            pfx_launch(sizeof(F) == 8, c, reduce, a, P.ptabs[c], red, P.pnblk[c], a.D, fan.stream(b++));
+        }
+    }
     const int* order = sizeof(F) == 4 ? kF32LaunchOrder : kF64LaunchOrder;
     for (int oc = 0; oc < ncls; ++oc) {
         const int c = order[oc];
@@ -614,13 +662,13 @@ thoi_status launch_eval(const double* Sigma, int64_t D, int32_t N, const thoi_np
     if (D == 0 || a.B == 0) return hip_status(hipGetLastError());
 
     if (opts->precision == THOI_FP64) {
-        Plan P = make_plan<double>(N, sel, reduce, opts->precision, opts->seg_tiles);
+        Plan P = make_plan<double>(N, D, sel, reduce, opts->precision, opts->seg_tiles, opts->engine);
         P.serial = serial;
         a.seg_tiles = P.seg_tiles;
         a.wave_tile = P.wave_tile;
         launch_forward<double>(a, sel, P, red, w, base, s);
     } else {
-        Plan P = make_plan<float>(N, sel, reduce, opts->precision, opts->seg_tiles);
+        Plan P = make_plan<float>(N, D, sel, reduce, opts->precision, opts->seg_tiles, opts->engine);
         P.serial = serial;
         a.seg_tiles = P.seg_tiles;
         a.wave_tile = P.wave_tile;
@@ -657,8 +705,8 @@ void eval_launch_shape(int32_t N, const thoi_nplets* sel, const thoi_eval_opts* 
                        int64_t* max_items_x)
 {
     const bool reduce = opts->reduce != nullptr;
-    const Plan P = opts->precision == THOI_FP64 ? make_plan<double>(N, sel, reduce, opts->precision, opts->seg_tiles)
-                                                : make_plan<float>(N, sel, reduce, opts->precision, opts->seg_tiles);
+    const Plan P = opts->precision == THOI_FP64 ? make_plan<double>(N, 1, sel, reduce, opts->precision, opts->seg_tiles, opts->engine)
+                                                : make_plan<float>(N, 1, sel, reduce, opts->precision, opts->seg_tiles, opts->engine);
     int n = 0;
     int64_t mx = 0;
     for (int c = 0; c < P.ncls; ++c) {
@@ -669,6 +717,11 @@ void eval_launch_shape(int32_t N, const thoi_nplets* sel, const thoi_eval_opts* 
     if (P.wblk) {
         ++n;
         mx = P.wblk * 64 > mx ? P.wblk * 64 : mx;
+    }
+    for (int c = 0; c < P.npcls; ++c) {
+        if (P.pnblk[c] == 0) continue;
+        ++n;
+        mx = P.pnblk[c] * kPfxThreads > mx ? P.pnblk[c] * kPfxThreads : mx;
     }
     *n_launches = n;
     *max_items_x = mx;

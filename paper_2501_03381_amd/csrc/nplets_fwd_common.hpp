@@ -6,30 +6,10 @@
 #include "reduce_common.hpp"
 
 namespace thoi {
-namespace {
 
-
-constexpr int kTile = 256;          // n-plets (= threads) per lane-engine tile
-constexpr int kMaxPieces = 24;      // orders per launch class
-constexpr int kWaveTileOut = 1;     // n-plets per wave-engine workgroup (output mode): spread the few, long factorisations over CUs
-constexpr int kWaveTileRed = 64;    // n-plets per wave-engine workgroup (reduce mode)
-constexpr int kListOrders = THOI_MAX_K + 2;   // k = 0..64 and one "invalid" bucket
-
-// Kernel classes: [lo, hi] of orders evaluated by one launch of the lane engine.
-struct KClass { int lo, hi; };
-constexpr KClass kF32Classes[] = {{0, 8}, {9, 12}, {13, 16}, {17, 20}, {21, 24}};
-constexpr KClass kF64Classes[] = {{0, 6}, {7, 10}, {11, 14}, {15, 18}};
-// Launch order of the classes of one evaluation.  The concurrent class grids start dispatching in
-// launch order, each once the previous one has placed its workgroups.  A class whose grid fits in
-// one round of waves but whose lanes run longest (FP32 orders 13..16 at N = 20) goes first, and
-// the largest grid fills the GPU around it.  FP64 keeps ascending order: its long classes need
-// several rounds at one wave per SIMD and, launched first, hold every SIMD.
-constexpr int kF32LaunchOrder[] = {2, 1, 3, 0, 4};
-constexpr int kF64LaunchOrder[] = {0, 1, 2, 3};
-static_assert(sizeof(kF32LaunchOrder) / sizeof(int) == sizeof(kF32Classes) / sizeof(KClass), "one entry per class");
-static_assert(sizeof(kF64LaunchOrder) / sizeof(int) == sizeof(kF64Classes) / sizeof(KClass), "one entry per class");
-constexpr int kF32LaneMax = 24;
-constexpr int kF64LaneMax = 18;
+// Argument structures of the forward kernels: defined outside the anonymous namespace (the same
+// definition in every translation unit) so that launchers in one unit can take them from another.
+inline constexpr int kMaxPieces = 24;      // orders per launch class
 
 struct Piece {
     int32_t k;
@@ -51,25 +31,6 @@ struct BiasParams {
     int32_t on, T;
     double psi1, psi2;
 };
-
-__device__ __forceinline__ void bias_for(const BiasParams& bp, int k, double& dtc, double& ddtc, double& eta)
-{
-    dtc = ddtc = eta = 0.0;
-    if (!bp.on || k <= 0) return;
-    double pm2 = bp.psi1, pm1 = bp.psi2;   // psi_{j-2}, psi_{j-1} as j advances
-    double P = 0.0, Pkm1 = 0.0, psik = bp.psi1;
-    for (int j = 1; j <= k; ++j) {
-        double pj;
-        if (j == 1) pj = bp.psi1;
-        else if (j == 2) pj = bp.psi2;
-        else { pj = pm2 - 2.0 / (double)(bp.T - j); pm2 = pm1; pm1 = pj; }
-        if (j == k) { Pkm1 = P; psik = pj; }
-        P += pj;
-    }
-    dtc = 0.5 * (P - k * bp.psi1);
-    ddtc = 0.5 * ((k - 1) * psik - Pkm1);
-    eta = 0.5 * (k * log(2.0 / (double)(bp.T - 1)) + P);
-}
 
 struct EvalArgs {
     const double* Sigma;
@@ -96,6 +57,49 @@ struct EvalArgs {
     const int64_t* lbase;    // [kListOrders] first slot in perm
     const int64_t* lblk0;    // [kListOrders] first workgroup of the order inside its launch
 };
+
+namespace {
+
+
+constexpr int kTile = 256;          // n-plets (= threads) per lane-engine tile
+constexpr int kWaveTileOut = 1;     // n-plets per wave-engine workgroup (output mode): spread the few, long factorisations over CUs
+constexpr int kWaveTileRed = 64;    // n-plets per wave-engine workgroup (reduce mode)
+constexpr int kListOrders = THOI_MAX_K + 2;   // k = 0..64 and one "invalid" bucket
+
+// Kernel classes: [lo, hi] of orders evaluated by one launch of the lane engine.
+struct KClass { int lo, hi; };
+constexpr KClass kF32Classes[] = {{0, 8}, {9, 12}, {13, 16}, {17, 20}, {21, 24}};
+constexpr KClass kF64Classes[] = {{0, 6}, {7, 10}, {11, 14}, {15, 18}};
+// Launch order of the classes of one evaluation.  The concurrent class grids start dispatching in
+// launch order, each once the previous one has placed its workgroups.  A class whose grid fits in
+// one round of waves but whose lanes run longest (FP32 orders 13..16 at N = 20) goes first, and
+// the largest grid fills the GPU around it.  FP64 keeps ascending order: its long classes need
+// several rounds at one wave per SIMD and, launched first, hold every SIMD.
+constexpr int kF32LaunchOrder[] = {2, 1, 3, 0, 4};
+constexpr int kF64LaunchOrder[] = {0, 1, 2, 3};
+static_assert(sizeof(kF32LaunchOrder) / sizeof(int) == sizeof(kF32Classes) / sizeof(KClass), "one entry per class");
+static_assert(sizeof(kF64LaunchOrder) / sizeof(int) == sizeof(kF64Classes) / sizeof(KClass), "one entry per class");
+constexpr int kF32LaneMax = 24;
+constexpr int kF64LaneMax = 18;
+
+__device__ __forceinline__ void bias_for(const BiasParams& bp, int k, double& dtc, double& ddtc, double& eta)
+{
+    dtc = ddtc = eta = 0.0;
+    if (!bp.on || k <= 0) return;
+    double pm2 = bp.psi1, pm1 = bp.psi2;   // psi_{j-2}, psi_{j-1} as j advances
+    double P = 0.0, Pkm1 = 0.0, psik = bp.psi1;
+    for (int j = 1; j <= k; ++j) {
+        double pj;
+        if (j == 1) pj = bp.psi1;
+        else if (j == 2) pj = bp.psi2;
+        else { pj = pm2 - 2.0 / (double)(bp.T - j); pm2 = pm1; pm1 = pj; }
+        if (j == k) { Pkm1 = P; psik = pj; }
+        P += pj;
+    }
+    dtc = 0.5 * (P - k * bp.psi1);
+    ddtc = 0.5 * ((k - 1) * psik - Pkm1);
+    eta = 0.5 * (k * log(2.0 / (double)(bp.T - 1)) + P);
+}
 
 // ------------------------------------------------------------------------------------------------
 // Result handling shared by the engines.  Returns whether the value may enter the reducer.
