@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libthoi.so")
-SOURCES = ["nplets_bwd_lane_hi.hip", "nplets_bwd_lane_lo.hip", "nplets_fwd.hip", "nplets_prefix.hip", "nplets_multi.hip",
+SOURCES = ["nplets_bwd_lane_hi.hip", "nplets_bwd_lane_lo.hip", "nplets_fwd.hip", "nplets_prefix.hip", "nplets_wave2.hip", "nplets_multi.hip",
            "api.cpp", "fan.cpp",
            "copula.hip", "cov.hip", "nplets_bwd.hip",
            "objective.hip", "noalloc.hip"]

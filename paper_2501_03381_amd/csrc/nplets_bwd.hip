@@ -403,7 +403,8 @@ thoi_status launch_backward(const double* Sigma, int64_t D, int32_t N, const tho
         hipLaunchKernelGGL(k_list_classify<THOI_SEL_LIST>, dim3(nb), dim3(256), 0, s, ea, 1, a.B, korder, cnt);
     else
         hipLaunchKernelGGL(k_list_classify<THOI_SEL_MASK>, dim3(nb), dim3(256), 0, s, ea, 1, a.B, korder, cnt);
-    hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(64), 0, s, cnt, lbase, lblk0, cursor, cm, (int64_t)1, (int64_t)1);
+    hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(64), 0, s, cnt, lbase, lblk0, cursor, cm, (int64_t)1, (int64_t)1,
+                       (int64_t)1);
     hipLaunchKernelGGL(k_list_scatter, dim3(nb), dim3(256), 0, s, a.B, korder, lbase, cursor, perm);
     launch_bwd_engines(a, sel, s);
     return hip_status(hipGetLastError());

@@ -15,6 +15,7 @@
 // Results go either to the output planes or to the streaming reducer (reduce_common.hpp).
 #include "nplets_fwd_common.hpp"
 #include "nplets_prefix.hpp"
+#include "nplets_wave2.hpp"
 
 namespace thoi {
 
@@ -97,11 +98,12 @@ __global__ __launch_bounds__(64) void k_eval_wave(EvalArgs a, PieceTable tab, Re
     const int N = a.N;
     const int d = blockIdx.y;
     const int64_t blk = blockIdx.x;
-    const int wt = a.wave_tile;
+    const int wt = a.wave_tile_hi;
     int k = -1;
     int64_t first = 0, pos0 = 0, cnt = 0, blk0 = 0;
     if constexpr (MODE == THOI_SEL_RANGE) {
         for (int p = 0; p < tab.n; ++p) {
+            if (tab.p[p].k < klo || tab.p[p].k > kmax) continue;   // another launch's orders
             const int64_t nb = (tab.p[p].cnt + wt - 1) / wt;
             if (blk >= tab.p[p].blk0 && blk < tab.p[p].blk0 + nb) {
                 k = tab.p[p].k; first = tab.p[p].first; pos0 = tab.p[p].pos0; cnt = tab.p[p].cnt; blk0 = tab.p[p].blk0;
@@ -184,86 +186,6 @@ __global__ __launch_bounds__(64) void k_eval_wave(EvalArgs a, PieceTable tab, Re
 }
 
 // ------------------------------------------------------------------------------------------------
-// Refinement: FP64 re-evaluation of the n-plets queued by the FP32 lane engine.
-// grid (G), block 64, grid-stride over the queue.  RANGE n-plets are unranked from the global
-// index; `ostart[k]` is the global index of the first n-plet of order k.
-// ------------------------------------------------------------------------------------------------
-struct RangeOrders {
-    int32_t kmin, kmax;
-    int64_t g_begin;
-    int64_t ostart[THOI_MAX_K + 2];
-};
-
-template <int MODE>
-__global__ __launch_bounds__(64) void k_refine(EvalArgs a, RangeOrders ro, RedArgs red, int kmax)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int N = a.N;
-    const int ks = kmax + 1;
-    double* sR = reinterpret_cast<double*>(smem);
-    double* sIsd = sR + N * N;
-    double* sLogd = sIsd + N;
-    uint64_t* sBin = reinterpret_cast<uint64_t*>(sLogd + N);
-    double* sM = reinterpret_cast<double*>(sBin + (MODE == THOI_SEL_RANGE ? N * 64 : 0));
-    double* sInv = sM + 64 * ks;
-    int* cidx = reinterpret_cast<int*>(sInv + 64);
-    __shared__ int sk;
-    // the queue is complete (the class kernels ran before this one); a workgroup without a
-    // queued n-plet leaves before staging anything
-    const uint32_t n = min(a.hdr->refine_count, a.refine_cap);
-    if (blockIdx.x >= n) return;
-    if constexpr (MODE == THOI_SEL_RANGE) stage_binomials(N, 64, sBin);
-    __syncthreads();
-    const int lane = threadIdx.x;
-    const bool reduce = red.active != 0;
-    int staged = -1;
-    for (uint32_t q = blockIdx.x; q < n; q += gridDim.x) {
-        const int64_t o = a.refine_list[q];
-        const int d = (int)(o / a.B);
-        const int64_t pos = o - (int64_t)d * a.B;
-        if (d != staged) {
-            stage_corr<double>(a.Sigma + (int64_t)d * N * N, N, sR, sIsd, sLogd);
-            staged = d;
-        }
-        if (lane == 0) {
-            int k = 0;
-            if constexpr (MODE == THOI_SEL_RANGE) {
-                const int64_t g = ro.g_begin + pos;
-                k = ro.kmin;
-                while (k < ro.kmax && g >= ro.ostart[k + 1]) ++k;
-                unrank_lex_rt((uint64_t)(g - ro.ostart[k]), N, k, sBin, 64, cidx);
-            } else if constexpr (MODE == THOI_SEL_LIST) {
-                const int32_t* row = a.idx + pos * a.kmax_list;
-                while (k < a.kmax_list && row[k] >= 0) { cidx[k] = row[k]; ++k; }
-            } else {
-                uint64_t m = a.mask[pos];
-                while (m) { cidx[k++] = __builtin_ctzll(m); m &= m - 1; }
-            }
-            sk = k;
-        }
-        __syncthreads();
-        const int k = sk;
-        const FactorOut<double> f = wave_factor(sR, N, cidx, k, sM, ks, sInv);
-        double sumlogd = 0.0;
-        if (a.write_H) sumlogd = wave_sum(lane < k ? sLogd[cidx[lane]] : 0.0);
-        if (lane == 0) {
-            EvalArgs b = a;
-            b.precision = THOI_FP64;
-            b.flags = nullptr;
-            double dtc, ddtc, eta, om = 0.0;
-            bias_for(a.bias, k, dtc, ddtc, eta);
-            const bool ok = store_result<double>(b, reduce, d, pos, k, f, sumlogd, dtc, ddtc, eta, true, om);
-            if (a.flags) a.flags[o] = (uint8_t)(THOI_NPLET_REFINED | (ok ? 0 : THOI_NPLET_NOT_PD));
-            if (reduce && ok) {
-                const int64_t g = MODE == THOI_SEL_RANGE ? ro.g_begin + pos : pos;
-                red_late(red, a.hdr, d, k, g, om);
-            }
-        }
-        __syncthreads();
-    }
-}
-
-// ------------------------------------------------------------------------------------------------
 // Host side
 // ------------------------------------------------------------------------------------------------
 // Launch plan of a call: workgroups per class and per wave launch; exact for RANGE, an upper
@@ -272,16 +194,22 @@ struct Plan {
     int ncls;
     PieceTable tabs[8];
     int64_t nblk[8];
-    PieceTable wtab;
-    int64_t wblk;
+    PieceTable wtab;     // RANGE pieces above the lane classes (pair and wave engines)
+    int64_t wblk;        // pair-engine workgroups (orders up to kW2Max)
+    int64_t wblk_hi;     // wave-engine workgroups (orders above kW2Max)
     int wkmax;
-    int seg_tiles, wave_tile;
+    int seg_tiles, wave_tile, wave_tile_hi;
     int64_t seg_cap;
     bool serial;     // every launch on the caller's stream (no side streams)
     int npcls;       // prefix engine: classes, their order tables and workgroups
     PfxTable ptabs[4];
     int64_t pnblk[4];
 };
+
+// Grids are kept well below the dispatch limit of 2^32 work-items along x: a class grid by
+// growing the tiles per workgroup, the wave grid by growing the n-plets per workgroup (both
+// engines loop over their share, so any tile count is valid).
+constexpr int64_t kMaxGridItems = int64_t(1) << 30;
 
 // Prefix engine for order k of this precision: the class index, or -1.
 int pfx_class_of(bool f64, int k)
@@ -320,7 +248,6 @@ Plan make_plan(int N, int64_t D, const thoi_nplets* sel, bool reduce, int precis
     const KClass* cls = classes_for<F>(P.ncls);
     const int lane_max = lane_max_for(precision);
     const int64_t Bn = sel_B(sel);
-    P.wave_tile = reduce ? kWaveTileRed : kWaveTileOut;
     // reduce mode: a workgroup walks a segment of tiles so that one launch has a few thousand
     // workgroups and the number of segments to merge stays bounded
     // FP64 ranges: two tiles per workgroup amortise the staging of the correlation matrix
@@ -333,8 +260,8 @@ Plan make_plan(int N, int64_t D, const thoi_nplets* sel, bool reduce, int precis
         if (P.seg_tiles < 1) P.seg_tiles = 1;
     }
     if (seg_tiles_hint > 0) P.seg_tiles = seg_tiles_hint;
-    // largest share of one class (or of the wave engine): n-plets per launch bound the grids
-    int64_t cls_cnt[8] = {0}, wave_cnt = 0;
+    // largest share of one class (or of the pair / wave engine): n-plets per launch bound the grids
+    int64_t cls_cnt[8] = {0}, pair_cnt = 0, wave_cnt = 0;
     if (sel->mode == THOI_SEL_RANGE) {
         int64_t g = 0;
         const int64_t gb = sel->g_begin, ge = sel->g_begin + sel->g_count;
@@ -343,13 +270,15 @@ Plan make_plan(int N, int64_t D, const thoi_nplets* sel, bool reduce, int precis
             const int64_t lo = gb > g ? gb : g, hi = ge < g + ck ? ge : g + ck;
             if (hi > lo && !prefix_order(k, lo, hi, g, ck)) {
                 if (k <= lane_max) cls_cnt[class_of<F>(k)] += hi - lo;
+                else if (k <= kW2Max) pair_cnt += hi - lo;
                 else wave_cnt += hi - lo;
             }
             g += ck;
         }
     } else {
         for (int c = 0; c < P.ncls; ++c) cls_cnt[c] = Bn;
-        if (sel_kmax(sel, N) > lane_max) wave_cnt = Bn;
+        if (sel_kmax(sel, N) > lane_max) pair_cnt = Bn;
+        if (sel_kmax(sel, N) > kW2Max) wave_cnt = Bn;
     }
     for (int c = 0; c < P.ncls; ++c) {
         // threads of class c at seg_tiles: about cls_cnt / (S * seg_tiles) plus one tile per piece
@@ -358,11 +287,29 @@ Plan make_plan(int N, int64_t D, const thoi_nplets* sel, bool reduce, int precis
         const int64_t need = (threads + kMaxGridItems - 1) / kMaxGridItems;
         if (need > P.seg_tiles) P.seg_tiles = (int)need;
     }
+    // pair engine: about 16384 workgroups in output mode and 8192 in reduce mode over all D
+    // datasets (each reducing workgroup leaves one segment of top-K lists to merge), at least one
+    // chunk of kPairThreads n-plets per reducing workgroup; a multiple of kPairHalves n-plets per
+    // workgroup
     {
-        const int64_t groups = (wave_cnt + P.wave_tile - 1) / P.wave_tile + kMaxPieces + 1;
+        int64_t groups = (reduce ? 8192 : 16384) / (D > 0 ? D : 1);
+        groups = groups < 64 ? 64 : groups;
+        const int64_t unit = reduce ? kPairThreads : kPairHalves;
+        int64_t t = (pair_cnt + groups - 1) / groups;
+        t = (t + unit - 1) / unit * unit;
+        t = t < unit ? unit : t;
+        const int64_t lim = kMaxGridItems / kPairThreads - kMaxPieces - 1;
+        if ((pair_cnt + t - 1) / t > lim) t = (pair_cnt + lim - 1) / lim;
+        P.wave_tile = (int)t;
+    }
+    // wave engine: one n-plet per workgroup in output mode (few, long factorisations), 64 in
+    // reduce mode; more when the grid would exceed its bound
+    P.wave_tile_hi = reduce ? kWaveTileRed : kWaveTileOut;
+    {
+        const int64_t groups = (wave_cnt + P.wave_tile_hi - 1) / P.wave_tile_hi + kMaxPieces + 1;
         if (groups * 64 > kMaxGridItems) {
             const int64_t t = (wave_cnt + kMaxGridItems / 64 - kMaxPieces - 2) / (kMaxGridItems / 64 - kMaxPieces - 1);
-            P.wave_tile = (int)(t > P.wave_tile ? t : P.wave_tile);
+            P.wave_tile_hi = (int)(t > P.wave_tile_hi ? t : P.wave_tile_hi);
         }
     }
     const int64_t per_blk = (int64_t)kTile * P.seg_tiles;     // one n-plet per lane (index lists)
@@ -395,9 +342,14 @@ Plan make_plan(int N, int64_t D, const thoi_nplets* sel, bool reduce, int precis
                     p.blk0 = P.nblk[c];
                     P.nblk[c] += (p.cnt + pb - 1) / pb;
                     P.tabs[c].p[P.tabs[c].n++] = p;
-                } else {
+                } else if (k <= kW2Max) {
                     p.blk0 = P.wblk;
                     P.wblk += (p.cnt + P.wave_tile - 1) / P.wave_tile;
+                    P.wtab.p[P.wtab.n++] = p;
+                    P.wkmax = k > P.wkmax ? k : P.wkmax;
+                } else {
+                    p.blk0 = P.wblk_hi;
+                    P.wblk_hi += (p.cnt + P.wave_tile_hi - 1) / P.wave_tile_hi;
                     P.wtab.p[P.wtab.n++] = p;
                     P.wkmax = k > P.wkmax ? k : P.wkmax;
                 }
@@ -408,11 +360,12 @@ Plan make_plan(int N, int64_t D, const thoi_nplets* sel, bool reduce, int precis
         for (int c = 0; c < P.ncls; ++c) P.nblk[c] = (Bn + per_blk - 1) / per_blk + (cls[c].hi - cls[c].lo + 1);
         const int kcap = sel_kmax(sel, N);
         if (kcap > lane_max) {
-            P.wblk = (Bn + P.wave_tile - 1) / P.wave_tile + (kcap - lane_max);
+            P.wblk = (Bn + P.wave_tile - 1) / P.wave_tile + ((kcap < kW2Max ? kcap : kW2Max) - lane_max);
             P.wkmax = kcap;
         }
+        if (kcap > kW2Max) P.wblk_hi = (Bn + P.wave_tile_hi - 1) / P.wave_tile_hi + (kcap - kW2Max);
     }
-    P.seg_cap = P.wblk;
+    P.seg_cap = P.wblk + P.wblk_hi;
     for (int c = 0; c < P.ncls; ++c) P.seg_cap += P.nblk[c];
     for (int c = 0; c < P.npcls; ++c) P.seg_cap += P.pnblk[c];
     return P;
@@ -507,7 +460,7 @@ void launch_engines(EvalArgs& a, const Plan& P, const RedArgs& red, hipStream_t 
     const bool reduce = red.active != 0;
     const int N = a.N;
     // the class launches are independent: fan them out over side streams
-    int nl = P.wblk ? 1 : 0;
+    int nl = (P.wblk ? 1 : 0) + (P.wblk_hi ? 1 : 0);
     for (int c = 0; c < ncls; ++c) nl += P.nblk[c] != 0;
     for (int c = 0; c < P.npcls; ++c) nl += P.pnblk[c] != 0;
     FanScope fan(s, P.serial ? 1 : nl);
@@ -528,12 +481,16 @@ void launch_engines(EvalArgs& a, const Plan& P, const RedArgs& red, hipStream_t 
         hipLaunchKernelGGL(kern, dim3((unsigned)P.nblk[c], (unsigned)a.D), dim3(kTile), lds, fan.stream(b++), a,
                            P.tabs[c], red);
     }
-    if (P.wblk) {
-        const int klo = MODE == THOI_SEL_RANGE ? 0 : lane_max_for(a.precision) + 1;
+    // orders above the lane engine: up to kW2Max two n-plets per wavefront (rows in registers),
+    // above that one per wavefront; each launch takes only its orders of the shared piece table
+    if (P.wblk)
+        pair_launch(MODE, reduce, a, P.wtab, red, lane_max_for(a.precision) + 1, P.wkmax < kW2Max ? P.wkmax : kW2Max,
+                    P.wblk, fan.stream(b++));
+    if (P.wblk_hi) {
         const size_t lds = wave_stage_bytes(N, P.wkmax, MODE == THOI_SEL_RANGE) + red_lds(reduce);
         const WaveKernel wk = wave_kernel<MODE>(reduce);
-        hipLaunchKernelGGL(wk, dim3((unsigned)P.wblk, (unsigned)a.D), dim3(64), lds, fan.stream(b++), a, P.wtab, red,
-                           klo, P.wkmax);
+        hipLaunchKernelGGL(wk, dim3((unsigned)P.wblk_hi, (unsigned)a.D), dim3(64), lds, fan.stream(b++), a, P.wtab,
+                           red, kW2Max + 1, P.wkmax);
     }
 }
 
@@ -558,11 +515,11 @@ void launch_list(EvalArgs& a, const Plan& P, const RedArgs& red, const EvalWs& w
     hipLaunchKernelGGL(k_list_classify<MODE>, dim3(nb), dim3(256), 0, s, a, red.active, Bn, korder, cnt);
     ClassMap cm{};
     for (int k = 0; k < kListOrders; ++k) {
-        cm.wave[k] = (k > lane_max) ? 1 : 0;
+        cm.wave[k] = (int8_t)(k > kW2Max ? 2 : (k > lane_max ? 1 : 0));
         cm.cls[k] = (int8_t)class_of<F>(k <= lane_max ? k : lane_max);
     }
     hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(64), 0, s, cnt, lbase, lblk0, cursor, cm,
-                       (int64_t)kTile * P.seg_tiles, (int64_t)P.wave_tile);
+                       (int64_t)kTile * P.seg_tiles, (int64_t)P.wave_tile, (int64_t)P.wave_tile_hi);
     hipLaunchKernelGGL(k_list_scatter, dim3(nb), dim3(256), 0, s, Bn, korder, lbase, cursor, perm);
     launch_engines<F, MODE>(a, P, red, s);
 }
@@ -594,12 +551,12 @@ size_t eval_lds_bytes(int32_t N, const thoi_nplets* sel, const thoi_eval_opts* o
     const int lane_max = lane_max_for(opts->precision);
     size_t need = lane_stage_bytes(N, range ? kF32LaneMax : 0, fsize) + red_lds(reduce);
     if (kmax > lane_max) {
-        const size_t w = wave_stage_bytes(N, kmax, range) + red_lds(reduce);
+        size_t w = pair_lds_bytes(N, reduce);
+        if (kmax > kW2Max) {
+            const size_t w2 = wave_stage_bytes(N, kmax, range) + red_lds(reduce);
+            w = w > w2 ? w : w2;
+        }
         need = need > w ? need : w;
-    }
-    if (opts->precision == THOI_FP32_REFINE) {
-        const size_t r = wave_stage_bytes(N, kmax, range);
-        need = need > r ? need : r;
     }
     return need;
 }
@@ -666,12 +623,14 @@ thoi_status launch_eval(const double* Sigma, int64_t D, int32_t N, const thoi_np
         P.serial = serial;
         a.seg_tiles = P.seg_tiles;
         a.wave_tile = P.wave_tile;
+        a.wave_tile_hi = P.wave_tile_hi;
         launch_forward<double>(a, sel, P, red, w, base, s);
     } else {
         Plan P = make_plan<float>(N, D, sel, reduce, opts->precision, opts->seg_tiles, opts->engine);
         P.serial = serial;
         a.seg_tiles = P.seg_tiles;
         a.wave_tile = P.wave_tile;
+        a.wave_tile_hi = P.wave_tile_hi;
         launch_forward<float>(a, sel, P, red, w, base, s);
     }
 
@@ -687,14 +646,8 @@ thoi_status launch_eval(const double* Sigma, int64_t D, int32_t N, const thoi_np
                 if (k <= sel->kmax) g += (int64_t)binom_u64(N, k);
             }
         }
-        const size_t lds = wave_stage_bytes(N, kmax, sel->mode == THOI_SEL_RANGE);
-        const unsigned G = 1024;
-        if (sel->mode == THOI_SEL_RANGE)
-            hipLaunchKernelGGL(k_refine<THOI_SEL_RANGE>, dim3(G), dim3(64), lds, s, a, ro, red, kmax);
-        else if (sel->mode == THOI_SEL_LIST)
-            hipLaunchKernelGGL(k_refine<THOI_SEL_LIST>, dim3(G), dim3(64), lds, s, a, ro, red, kmax);
-        else
-            hipLaunchKernelGGL(k_refine<THOI_SEL_MASK>, dim3(G), dim3(64), lds, s, a, ro, red, kmax);
+        // every queued n-plet comes from an FP32 lane class (order <= 24)
+        pair_refine_launch(sel->mode, a, ro, red, 1024, s);
     }
     if (reduce && red.topk > 0)
         hipLaunchKernelGGL(k_red_final, dim3((unsigned)(kmax + 1), (unsigned)D), dim3(256), 0, s, red, a.hdr);
@@ -716,7 +669,11 @@ void eval_launch_shape(int32_t N, const thoi_nplets* sel, const thoi_eval_opts* 
     }
     if (P.wblk) {
         ++n;
-        mx = P.wblk * 64 > mx ? P.wblk * 64 : mx;
+        mx = P.wblk * kPairThreads > mx ? P.wblk * kPairThreads : mx;
+    }
+    if (P.wblk_hi) {
+        ++n;
+        mx = P.wblk_hi * 64 > mx ? P.wblk_hi * 64 : mx;
     }
     for (int c = 0; c < P.npcls; ++c) {
         if (P.pnblk[c] == 0) continue;

@@ -32,6 +32,13 @@ struct BiasParams {
     double psi1, psi2;
 };
 
+// RANGE refinement: the orders of the call and the global index of the first n-plet of each.
+struct RangeOrders {
+    int32_t kmin, kmax;
+    int64_t g_begin;
+    int64_t ostart[THOI_MAX_K + 2];
+};
+
 struct EvalArgs {
     const double* Sigma;
     int32_t N, D;
@@ -46,7 +53,8 @@ struct EvalArgs {
     int64_t* refine_list;
     uint32_t refine_cap;
     int32_t seg_tiles;       // lane engine: tiles of kTile n-plets per workgroup
-    int32_t wave_tile;       // wave engine: n-plets per workgroup
+    int32_t wave_tile;       // pair engine (orders up to 32 above the lane classes): n-plets per workgroup
+    int32_t wave_tile_hi;    // wave engine (orders above 32): n-plets per workgroup
     BiasParams bias;
     // LIST / MASK
     const int32_t* idx;
@@ -426,12 +434,13 @@ __global__ __launch_bounds__(256) void k_list_classify(EvalArgs a, int reduce, i
         if (h[i]) atomicAdd(&cnt[i], (unsigned long long)h[i]);
 }
 
+// per order: lane-engine class, and 0 (lane engine), 1 (pair engine) or 2 (wave engine)
 struct ClassMap { int8_t cls[kListOrders]; int8_t wave[kListOrders]; };
 
 // 1 workgroup: per-order base in perm, and first workgroup of each order inside its launch.
 __global__ void k_list_scan(const unsigned long long* __restrict__ cnt, int64_t* __restrict__ base,
                             int64_t* __restrict__ blk0, unsigned long long* __restrict__ cursor, ClassMap cm,
-                            int64_t per_lane_blk, int64_t per_wave_blk)
+                            int64_t per_lane_blk, int64_t per_pair_blk, int64_t per_wave_blk)
 {
     // One thread per order loads its count and class, and divides the count into workgroups (a
     // 64-bit division is a long instruction sequence); one thread then scans in LDS only (byte reads
@@ -442,11 +451,11 @@ __global__ void k_list_scan(const unsigned long long* __restrict__ cnt, int64_t*
     __shared__ int8_t wv[kListOrders], cl[kListOrders];
     for (int k = threadIdx.x; k < kListOrders; k += blockDim.x) {
         const int64_t ck = (int64_t)cnt[k];
-        const bool w = cm.wave[k] != 0;
+        const int w = cm.wave[k];
         c[k] = ck;
-        wv[k] = w ? 1 : 0;
+        wv[k] = (int8_t)w;
         cl[k] = cm.cls[k];
-        const int64_t per = w ? per_wave_blk : per_lane_blk;
+        const int64_t per = w == 2 ? per_wave_blk : (w == 1 ? per_pair_blk : per_lane_blk);
         nb[k] = k > THOI_MAX_K ? 0 : (ck + per - 1) / per;
         cursor[k] = 0;
     }
@@ -454,14 +463,17 @@ __global__ void k_list_scan(const unsigned long long* __restrict__ cnt, int64_t*
     __syncthreads();
     if (threadIdx.x == 0) {
         int64_t b = 0;
-        int64_t wt = 0;
+        int64_t wp = 0, ww = 0;
         for (int k = 0; k < kListOrders; ++k) {
             sb[k] = b;
             b += c[k];
             if (k > THOI_MAX_K) { sk[k] = 0; continue; }
-            if (wv[k]) {
-                sk[k] = wt;
-                wt += nb[k];
+            if (wv[k] == 1) {
+                sk[k] = wp;
+                wp += nb[k];
+            } else if (wv[k] == 2) {
+                sk[k] = ww;
+                ww += nb[k];
             } else {
                 sk[k] = ct[cl[k]];
                 ct[cl[k]] += nb[k];

@@ -1,0 +1,407 @@
+// Pair engine: FP64 evaluation of n-plets whose order is above the register classes (up to 32),
+// two n-plets per wavefront.
+//
+// Each half-wave (32 lanes) factors one n-plet; lane i keeps row i of the sub-matrix in registers
+// (32 doubles, indexed by compile-time constants only: every loop below is unrolled to order 32
+// and guarded by the runtime order, which is the same for the whole wavefront).  Right-looking
+// Cholesky: at step j the lanes i >= j publish a_ij in LDS, every lane reads the pivot and the
+// column, scales its entry and updates its row.  W = L^-1 by forward substitution, one row per
+// step: lane t publishes row t of W in LDS, the later rows accumulate L_it W_t, and every lane j
+// adds W_tj^2 to the squared norm of column j, which is a_j = (R_S^-1)_jj.  log det and
+// sum log a_j are half-wave sums, max a_j a half-wave maximum.  The measures follow as in the
+// lane engine (TC = -ld/2, DTC = (ld + sum log a_j)/2, Omega, S; Methods, entropy terms of the
+// Gaussian copula).  Only the lanes of one wavefront exchange data through LDS, so a wavefront
+// needs no workgroup barrier: LDS operations of one wavefront complete in issue order, and a
+// wavefront-scope fence keeps the compiler from reordering them.
+#include "nplets_wave2.hpp"
+
+namespace thoi {
+namespace {
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double half_sum(double v)
+{
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 32);
+    return v;
+}
+__device__ __forceinline__ double half_max(double v)
+{
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) {
+        const double u = __shfl_xor(v, o, 32);
+        v = v > u ? v : u;
+    }
+    return v;
+}
+
+// Factor the n-plet cidx[0..kh-1] of this half-wave (lane i = row i).  Both halves of the
+// wavefront pass the same k (>= the kh of each): the loops run to k.  GLOBAL: entries from the
+// covariance Sig in global memory, scaled by 1/sqrt(Sigma_ii Sigma_jj) (each half may have its
+// own dataset); otherwise from the staged correlation matrix sR.  col and wrow: two buffers of 32
+// doubles each, per half.  Returns the FactorOut in every lane.
+template <bool GLOBAL>
+__device__ __forceinline__ FactorOut<double> pair_factor(const double* __restrict__ sR, int N,
+                                                         const int* __restrict__ cidx, int k_in, int kh,
+                                                         double* __restrict__ col, double* __restrict__ wrow)
+{
+    const int k = __builtin_amdgcn_readfirstlane(k_in);   // uniform: scalar loop guards
+    const int i = threadIdx.x & 31;
+    const bool mine = i < kh;
+    const int ci = mine ? cidx[i] : 0;
+    double r[kW2Max];
+    double si = 1.0;
+    if constexpr (GLOBAL) {
+        const double di = sR[(int64_t)ci * N + ci];
+        si = di > 0.0 ? 1.0 / sqrt(di) : __builtin_nan("");
+    }
+    // every loop below is unrolled by sfor, so r[] is indexed by constants only
+    sfor<0, kW2Max>([&](auto M) {
+        constexpr int m = M;
+        double v = 0.0;
+        if (m < k && m < i && mine) {
+            const int cm = cidx[m];
+            if constexpr (GLOBAL) {
+                const double dm = sR[(int64_t)cm * N + cm];
+                v = sR[(int64_t)ci * N + cm] * si * (dm > 0.0 ? 1.0 / sqrt(dm) : __builtin_nan(""));
+            } else {
+                v = sR[ci * N + cm];
+            }
+        }
+        r[m] = (m == i && mine) ? 1.0 : v;
+    });
+    // Right-looking Cholesky.  Lane i's entries r[m] with m > i, and every entry of a lane beyond
+    // the order, are never read for the result; the updates below run on them too, so that the
+    // inner loops need no per-lane condition (column entries beyond the order are stale but in
+    // bounds).  The update loops are guarded in groups of four columns by the uniform order.
+    double piv = 1.0;
+    sfor<0, kW2Max>([&](auto J) {
+        constexpr int j = J;
+        if (j < k) {
+            double* cl = col + (j & 1) * kW2Max;
+            cl[i] = r[j];                                 // a_ij of the current Schur complement
+            wave_sync();
+            const double p = cl[j];
+            const double rs = rsqrt(p);
+            const double aij = r[j];
+            const double t = aij * rs * rs;               // a_ij / a_jj
+            piv = i == j ? p : piv;
+            r[j] = i == j ? rs : aij * rs;                // 1 / L_jj on the diagonal, L_ij below
+            sfor<(j + 1) / 4, kW2Max / 4>([&](auto G) {
+                constexpr int g = G;
+                if (4 * g < k) {
+                    sfor<4 * g, 4 * g + 4>([&](auto M) {
+                        constexpr int m = M;
+                        if constexpr (m > j) r[m] -= t * cl[m];
+                    });
+                }
+            });
+        }
+    });
+    // W = L^-1 row by row.  Lane i holds L_im in r[m] (m < i) and 1 / L_ii in r[i]; at step t it
+    // adds L_it W_t to the running sum of its row, stored in r[0..t] as L_it is consumed (a lane
+    // whose row is published no longer needs its registers).  Column norms accumulate in aj.
+    double aj = 0.0;
+    sfor<0, kW2Max>([&](auto T) {
+        constexpr int t = T;
+        if (t < k) {
+            double* wr = wrow + (t & 1) * kW2Max;
+            if (i == t) {
+                sfor<0, t + 1>([&](auto M) {
+                    constexpr int m = M;
+                    wr[m] = m < t ? -r[m] * r[t] : r[t];
+                });
+            }
+            wave_sync();
+            const double w = wr[i];
+            aj += (i <= t && t < kh) ? w * w : 0.0;      // rows of this half's own n-plet only
+            const double lit = r[t];
+            sfor<0, t>([&](auto M) {
+                constexpr int m = M;
+                r[m] += lit * wr[m];
+            });
+            r[t] = lit * wr[t];
+        }
+    });
+    FactorOut<double> o;
+    o.ld = half_sum(mine ? log(piv) : 0.0);
+    o.sa = half_sum(mine ? log(aj) : 0.0);
+    o.vmax = half_max(mine ? aj : 0.0);
+    o.ok = half_sum((mine && !(piv > 0.0)) ? 1.0 : 0.0) == 0.0;
+    wave_sync();
+    return o;
+}
+
+// Lexicographic unranking of rank r among the k-subsets of {0..N-1} (one lane), binomials from the
+// compile-time table.
+__device__ __forceinline__ void pair_unrank(uint64_t r, int N, int k, int* __restrict__ c)
+{
+    int x = 0;
+    for (int i = 0; i < k; ++i) {
+        const int m = k - 1 - i;
+        while (x < N) {
+            const uint64_t b = kPascal.v[N - 1 - x][m];
+            if (r < b) break;
+            r -= b;
+            ++x;
+        }
+        c[i] = x++;
+    }
+}
+
+// LDS: sR [N*N] f64 | sIsd [N] | sLogd [N] | col [8 halves][2][32] f64 | wrow [8][2][32] f64 |
+//      cidx [8][32] int | (reduce) res_v [256] f64 | res_g [256] i64 | res_ok [256] int | RedLds
+__host__ __device__ inline size_t w2_stage_bytes(int N, bool reduce)
+{
+    size_t off = (size_t)N * N * 8 + (size_t)N * 16;
+    off += 2 * kPairHalves * 2 * (size_t)kW2Max * 8 + kPairHalves * (size_t)kW2Max * 4;
+    if (reduce) off += (size_t)kPairThreads * (8 + 8 + 4);
+    return (off + 15) / 16 * 16;
+}
+
+// grid (workgroups, D), block kPairThreads.  A workgroup takes a.wave_tile n-plets of one order k
+// in chunks of up to kPairThreads; in a chunk each half-wave evaluates a run of consecutive
+// n-plets (lexicographic successors in RANGE mode, so only the first of a run is unranked).  In
+// reduce mode the chunk's results go to the workgroup's reducer together.
+template <int MODE, bool RED>
+__global__ __launch_bounds__(kPairThreads) void k_eval_pair(EvalArgs a, PieceTable tab, RedArgs red, int klo, int kmax)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double sbias[3];
+    const int N = a.N;
+    const int d = blockIdx.y;
+    const int64_t blk = blockIdx.x;
+    const int wt = a.wave_tile;
+    int k = -1;
+    int64_t first = 0, pos0 = 0, cnt = 0, blk0 = 0;
+    if constexpr (MODE == THOI_SEL_RANGE) {
+        for (int p = 0; p < tab.n; ++p) {
+            if (tab.p[p].k < klo || tab.p[p].k > kmax) continue;   // another launch's orders
+            const int64_t nb = (tab.p[p].cnt + wt - 1) / wt;
+            if (blk >= tab.p[p].blk0 && blk < tab.p[p].blk0 + nb) {
+                k = tab.p[p].k; first = tab.p[p].first; pos0 = tab.p[p].pos0; cnt = tab.p[p].cnt; blk0 = tab.p[p].blk0;
+            }
+        }
+    } else {
+        for (int kk = klo; kk <= kmax; ++kk) {
+            const int64_t c = a.lcnt[kk];
+            const int64_t nb = (c + wt - 1) / wt;
+            const int64_t b0 = a.lblk0[kk];
+            if (c > 0 && blk >= b0 && blk < b0 + nb) { k = kk; first = a.lbase[kk]; cnt = c; blk0 = b0; }
+        }
+    }
+    if (k < 0) return;
+    double* sR = reinterpret_cast<double*>(smem);
+    double* sIsd = sR + N * N;
+    double* sLogd = sIsd + N;
+    double* scol = sLogd + N;
+    double* swrow = scol + kPairHalves * 2 * kW2Max;
+    int* scidx = reinterpret_cast<int*>(swrow + kPairHalves * 2 * kW2Max);
+    double* res_v = reinterpret_cast<double*>(scidx + kPairHalves * kW2Max);
+    int64_t* res_g = reinterpret_cast<int64_t*>(res_v + kPairThreads);
+    int* res_ok = reinterpret_cast<int*>(res_g + kPairThreads);
+    RedLds& S = *reinterpret_cast<RedLds*>(smem + w2_stage_bytes(N, RED));
+    if (threadIdx.x == 0) bias_for(a.bias, k, sbias[0], sbias[1], sbias[2]);
+    stage_corr<double>(a.Sigma + (int64_t)d * N * N, N, sR, sIsd, sLogd);
+    if constexpr (RED) red_begin(S, red.topk, red.bins);
+    __syncthreads();
+
+    const int q = threadIdx.x >> 5, i = threadIdx.x & 31, h = q & 1;
+    int* ch = scidx + q * kW2Max;
+    double* col = scol + q * 2 * kW2Max;
+    double* wrow = swrow + q * 2 * kW2Max;
+    const int64_t l0 = (blk - blk0) * wt;
+    const int64_t l1 = l0 + wt < cnt ? l0 + wt : cnt;
+    for (int64_t c0 = l0; c0 < l1; c0 += kPairThreads) {
+        const int64_t c1 = c0 + kPairThreads < l1 ? c0 + kPairThreads : l1;
+        const int run = (int)((c1 - c0 + kPairHalves - 1) / kPairHalves);
+        const int64_t r0 = c0 + (int64_t)q * run;
+        const int64_t r1 = r0 + run < c1 ? r0 + run : c1;
+        // the wavefront's two halves step together; an exhausted half factors a dummy
+        const int64_t o_r0 = c0 + (int64_t)(q ^ 1) * run;
+        const int64_t o_r1 = o_r0 + run < c1 ? o_r0 + run : c1;
+        const int n_me = (int)(r1 > r0 ? r1 - r0 : 0), n_other = (int)(o_r1 > o_r0 ? o_r1 - o_r0 : 0);
+        const int steps = n_me > n_other ? n_me : n_other;
+        int ci = i;                              // lane i's variable (RANGE: kept across the run)
+        if constexpr (MODE == THOI_SEL_RANGE) {
+            if (r0 < r1) {
+                if (i == 0) pair_unrank((uint64_t)(first + r0), N, k, ch);
+                wave_sync();
+                ci = i < k ? ch[i] : i;
+            }
+        }
+        for (int it = 0; it < steps; ++it) {
+            const int64_t my = r0 + it;
+            const bool act = my < r1;
+            int64_t pos = 0, gidx = 0;
+            if (act) {
+                if constexpr (MODE == THOI_SEL_RANGE) {
+                    pos = pos0 + my;
+                    gidx = a.g_begin + pos;
+                    if (it > 0) {
+                        // lexicographic successor: the last position that can grow grows, the later
+                        // ones follow it
+                        const bool can = i < k && ci < N - k + i;
+                        const uint32_t bits = (uint32_t)(__ballot(can) >> (32 * h));
+                        const int p = 31 - __builtin_clz(bits | 1u);
+                        const int cp = __shfl(ci, p, 32);
+                        if (i >= p && i < k) ci = cp + 1 + (i - p);
+                    }
+                } else if constexpr (MODE == THOI_SEL_LIST) {
+                    pos = a.perm[first + my];
+                    gidx = pos;
+                    if (i < k) ci = a.idx[pos * a.kmax_list + i];
+                } else {
+                    pos = a.perm[first + my];
+                    gidx = pos;
+                    uint64_t m = a.mask[pos];
+                    // lane i takes the (i+1)-th set bit
+                    for (int t = 0; t < i && m; ++t) m &= m - 1;
+                    if (i < k) ci = __builtin_ctzll(m);
+                }
+            } else {
+                ci = i;                          // variables 0..k-1; the result is discarded
+            }
+            if (i < k) ch[i] = ci;
+            wave_sync();
+            const FactorOut<double> f = pair_factor<false>(sR, N, ch, k, k, col, wrow);
+            double sumlogd = 0.0;
+            if (a.write_H) sumlogd = half_sum(i < k ? sLogd[ci] : 0.0);
+            if (i == 0 && act) {
+                double om = 0.0;
+                // FP64 already: never queued for refinement
+                EvalArgs b = a;
+                if (b.precision == THOI_FP32_REFINE) b.precision = THOI_FP64;
+                const bool ok = store_result<double>(b, RED, d, pos, k, f, sumlogd, sbias[0], sbias[1], sbias[2], true, om);
+                if constexpr (RED) {
+                    const int slot = (int)(my - c0);
+                    res_v[slot] = om;
+                    res_g[slot] = gidx;
+                    res_ok[slot] = ok;
+                }
+            }
+            wave_sync();
+        }
+        if constexpr (RED) {
+            __syncthreads();
+            const int t = threadIdx.x;
+            const bool have = c0 + t < c1;
+            red_push(S, red, k, have && res_ok[t], have ? res_v[t] : 0.0, have ? res_g[t] : 0);
+            __syncthreads();
+        }
+    }
+    if constexpr (RED) red_end(S, red, a.hdr, d, k);
+}
+
+// FP64 re-evaluation of the n-plets queued by the FP32 lane engine, two per wavefront (each half
+// its own queue entry, order and dataset; entries read from Sigma in global memory).  grid (G),
+// block 64, grid-stride over pairs of queue entries; the queue is complete (the class kernels ran
+// before this one) and a workgroup with no entry leaves at once.
+template <int MODE>
+__global__ __launch_bounds__(64) void k_refine_pair(EvalArgs a, RangeOrders ro, RedArgs red)
+{
+    __shared__ double scol[2 * 2 * kW2Max];
+    __shared__ double swrow[2 * 2 * kW2Max];
+    __shared__ int cidx[2 * kW2Max];
+    __shared__ int sk[2];
+    const int N = a.N;
+    const uint32_t n = min(a.hdr->refine_count, a.refine_cap);
+    const int h = threadIdx.x >> 5, i = threadIdx.x & 31;
+    int* ch = cidx + h * kW2Max;
+    double* col = scol + h * 2 * kW2Max;
+    double* wrow = swrow + h * 2 * kW2Max;
+    const bool reduce = red.active != 0;
+    for (uint32_t q0 = 2 * blockIdx.x; q0 < n; q0 += 2 * gridDim.x) {
+        const uint32_t q = q0 + h;
+        const bool act = q < n;
+        int64_t o = 0, pos = 0;
+        int d = 0;
+        if (act) {
+            o = a.refine_list[q];
+            d = (int)(o / a.B);
+            pos = o - (int64_t)d * a.B;
+        }
+        if (i == 0) {
+            int k = 0;
+            if (act) {
+                if constexpr (MODE == THOI_SEL_RANGE) {
+                    const int64_t g = ro.g_begin + pos;
+                    k = ro.kmin;
+                    while (k < ro.kmax && g >= ro.ostart[k + 1]) ++k;
+                    k = k < kW2Max ? k : kW2Max;   // queued n-plets are of order <= 24
+                    pair_unrank((uint64_t)(g - ro.ostart[k]), N, k, ch);
+                } else if constexpr (MODE == THOI_SEL_LIST) {
+                    const int32_t* row = a.idx + pos * a.kmax_list;
+                    while (k < a.kmax_list && k < kW2Max && row[k] >= 0) { ch[k] = row[k]; ++k; }
+                } else {
+                    uint64_t m = a.mask[pos];
+                    while (m && k < kW2Max) { ch[k++] = __builtin_ctzll(m); m &= m - 1; }
+                }
+            }
+            sk[h] = k;
+        }
+        __syncthreads();
+        const int kh = sk[h];
+        const int kk = sk[0] > sk[1] ? sk[0] : sk[1];
+        const FactorOut<double> f = pair_factor<true>(a.Sigma + (int64_t)d * N * N, N, ch, kk, kh, col, wrow);
+        double sumlogd = 0.0;
+        if (a.write_H) {
+            const double* Sg = a.Sigma + (int64_t)d * N * N;
+            sumlogd = half_sum(i < kh ? log(Sg[(int64_t)ch[i] * N + ch[i]]) : 0.0);
+        }
+        if (i == 0 && act) {
+            EvalArgs b = a;
+            b.precision = THOI_FP64;
+            b.flags = nullptr;
+            double dtc, ddtc, eta, om = 0.0;
+            bias_for(a.bias, kh, dtc, ddtc, eta);
+            const bool ok = store_result<double>(b, reduce, d, pos, kh, f, sumlogd, dtc, ddtc, eta, true, om);
+            if (a.flags) a.flags[o] = (uint8_t)(THOI_NPLET_REFINED | (ok ? 0 : THOI_NPLET_NOT_PD));
+            if (reduce && ok) {
+                const int64_t g = MODE == THOI_SEL_RANGE ? ro.g_begin + pos : pos;
+                red_late(red, a.hdr, d, kh, g, om);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+void pair_refine_launch(int mode, const EvalArgs& a, const RangeOrders& ro, const RedArgs& red, unsigned G,
+                        hipStream_t s)
+{
+    if (mode == THOI_SEL_RANGE) hipLaunchKernelGGL(k_refine_pair<THOI_SEL_RANGE>, dim3(G), dim3(64), 0, s, a, ro, red);
+    else if (mode == THOI_SEL_LIST) hipLaunchKernelGGL(k_refine_pair<THOI_SEL_LIST>, dim3(G), dim3(64), 0, s, a, ro, red);
+    else hipLaunchKernelGGL(k_refine_pair<THOI_SEL_MASK>, dim3(G), dim3(64), 0, s, a, ro, red);
+}
+
+size_t pair_lds_bytes(int N, bool reduce)
+{
+    return w2_stage_bytes(N, reduce) + (reduce ? sizeof(RedLds) : 0);
+}
+
+void pair_launch(int mode, bool reduce, const EvalArgs& a, const PieceTable& t, const RedArgs& red, int klo, int kmax,
+                 int64_t nblk, hipStream_t s)
+{
+    const size_t lds = pair_lds_bytes(a.N, reduce);
+    const dim3 grid((unsigned)nblk, (unsigned)a.D);
+    if (mode == THOI_SEL_RANGE) {
+        if (reduce) hipLaunchKernelGGL((k_eval_pair<THOI_SEL_RANGE, true>), grid, dim3(kPairThreads), lds, s, a, t, red, klo, kmax);
+        else hipLaunchKernelGGL((k_eval_pair<THOI_SEL_RANGE, false>), grid, dim3(kPairThreads), lds, s, a, t, red, klo, kmax);
+    } else if (mode == THOI_SEL_LIST) {
+        if (reduce) hipLaunchKernelGGL((k_eval_pair<THOI_SEL_LIST, true>), grid, dim3(kPairThreads), lds, s, a, t, red, klo, kmax);
+        else hipLaunchKernelGGL((k_eval_pair<THOI_SEL_LIST, false>), grid, dim3(kPairThreads), lds, s, a, t, red, klo, kmax);
+    } else {
+        if (reduce) hipLaunchKernelGGL((k_eval_pair<THOI_SEL_MASK, true>), grid, dim3(kPairThreads), lds, s, a, t, red, klo, kmax);
+        else hipLaunchKernelGGL((k_eval_pair<THOI_SEL_MASK, false>), grid, dim3(kPairThreads), lds, s, a, t, red, klo, kmax);
+    }
+}
+
+}  // namespace thoi

@@ -253,6 +253,80 @@ def test_wave_engine_large_orders(env):
             assert_close(out[m, pick], ref[m], tol, f"{prec} m={m}")
 
 
+def test_pair_and_wave_engines_split_at_32(env):
+    """Orders 19..32 (FP64) run two n-plets per wavefront, orders above 32 one per wavefront: a
+    RANGE, a LIST and a MASK selection spanning both are split between the two launches with no
+    n-plet lost or evaluated twice."""
+    torch, api, B, synth, orc = env
+    rng = np.random.default_rng(16)
+    N, kmin = 36, 30
+    S = orc.gc_covariance(synth.ar1_30(N=N, T=3000))
+    Sd = dev(torch, S)
+    total = B.thoi_count(N, kmin, N)
+    pick = np.unique(np.concatenate([rng.integers(0, total, 800), np.arange(300), np.arange(total - 400, total)]))
+    rows = orc.pad_list([lex_unrank(int(p), N, kmin) for p in pick], kmax=N)
+    ref, _, _ = orc.eval_list(S, rows)
+    for prec, tol, odt in (("fp64", TOL64, torch.float64), ("fp32_refine", TOL32, torch.float32)):
+        say(f"RANGE {prec} N={N} orders {kmin}..{N} ({total} n-plets)")
+        out, flags = api.nplets_measures(Sd, orders=(kmin, N), precision=prec, out_dtype=odt)
+        out = host(out)
+        assert np.all(host(flags) & B.THOI_NPLET_NOT_PD == 0)
+        for m in range(4):
+            assert_close(out[m, pick], ref[m], tol, f"RANGE {prec} m={m}")
+    # LIST rows of orders 19..40 in random order over N = 48, and 64-bit masks over N = 40
+    X48 = synth.ar1_30(N=48, T=3000, seed=5)
+    S48 = orc.gc_covariance(X48)
+    ks = rng.integers(19, 41, 900)
+    lst = orc.pad_list([sorted(rng.choice(48, k, replace=False).tolist()) for k in ks], kmax=40)
+    ref_l, _, _ = orc.eval_list(S48, lst)
+    S40 = S48[:40, :40].copy()
+    masks = np.array([sum(1 << int(j) for j in rng.choice(40, k, replace=False)) for k in rng.integers(19, 41, 700)],
+                     dtype=np.uint64).astype(np.int64)
+    mrows = orc.pad_list([[j for j in range(40) if (int(m) >> j) & 1] for m in masks.astype(np.uint64)], kmax=40)
+    ref_m, _, _ = orc.eval_list(S40, mrows)
+    for prec, tol, odt in (("fp64", TOL64, torch.float64), ("fp32_refine", TOL32, torch.float32)):
+        say(f"LIST {prec} N=48 orders 19..40 B=900")
+        out, _ = api.nplets_measures(dev(torch, S48), nplets=dev(torch, lst), precision=prec, out_dtype=odt)
+        out = host(out)
+        for m in range(4):
+            assert_close(out[m], ref_l[m], tol, f"LIST {prec} m={m}")
+        say(f"MASK {prec} N=40 popcount 19..40 B=700")
+        out, _ = api.nplets_measures(dev(torch, S40), masks=dev(torch, masks), precision=prec, out_dtype=odt)
+        out = host(out)
+        for m in range(4):
+            assert_close(out[m], ref_m[m], tol, f"MASK {prec} m={m}")
+
+
+def test_refinement_pairs_mixed_orders_and_datasets(env):
+    """The FP64 re-evaluation takes two queued n-plets per wavefront, which may differ in order
+    and dataset: near-duplicate columns in two datasets, LIST rows of orders 3..24."""
+    torch, api, B, synth, orc = env
+    rng = np.random.default_rng(17)
+    Ss = []
+    for d, (i, j) in enumerate(((0, 1), (5, 9))):
+        X, _ = synth.latent_100(seed=20 + d, B=1)
+        X = X[:, :40].copy()
+        X[:, j] = X[:, i] + 1e-4 * rng.standard_normal(X.shape[0])
+        Ss.append(orc.gc_covariance(X))
+    S = np.stack(Ss)
+    ks = rng.integers(3, 25, 1500)
+    rows = []
+    for r, k in enumerate(ks):
+        base = [0, 1, 5, 9] if r % 2 == 0 else []
+        rest = [x for x in rng.permutation(40).tolist() if x not in base][:max(k - len(base), 0)]
+        rows.append(sorted((base + rest)[:k]))
+    idx = orc.pad_list(rows, kmax=24)
+    say("LIST fp32_refine D=2 N=40 orders 3..24 with near-duplicate columns")
+    out, flags = api.nplets_measures(dev(torch, S), nplets=dev(torch, idx), precision="fp32_refine",
+                                     out_dtype=torch.float64)
+    out, flags = host(out), host(flags)
+    assert ((flags & B.THOI_NPLET_REFINED) != 0).sum() > 200
+    for d in range(2):
+        ref, _, _ = orc.eval_list(S[d], idx)
+        for m in range(4):
+            assert_close(out[m, d], ref[m], TOL32, f"d={d} m={m}")
+
+
 # ------------------------------------------------------------------------------------------------ LIST / MASK
 def test_eval_list_mixed_orders_n100(env):
     torch, api, B, synth, orc = env

@@ -9,6 +9,7 @@ Two kinds of check:
   being allowed on either side of an edge only when the oracle puts it within the tolerance of
   that edge (1e-9 for the FP64 path, 1e-3 for FP32 with refinement).
 """
+import math
 import sys
 
 import numpy as np
@@ -141,6 +142,26 @@ def test_reduce_list_mixed_orders_and_wave_engine(env):
         check_lists(tv[0], tg[0], om, ords, 20, 0.0)
         for k in range(8, 21):
             assert np.array_equal(h[0, k], orc.histogram(om[ords == k], -4.0, 4.0, 40)), k
+
+
+def test_reduce_range_pair_and_wave_engines(env):
+    """Orders 19..32 of a FP64 reduction run two n-plets per wavefront, orders 33..36 one per
+    wavefront; both feed the reducer exactly what the full-output run writes."""
+    torch, api, B, synth, orc = env
+    N, kmin = 36, 30
+    Sd = dev(torch, orc.gc_covariance(synth.ar1_30(N=N, T=3000)))
+    total = B.thoi_count(N, kmin, N)
+    ords = np.concatenate([np.full(math.comb(N, k), k) for k in range(kmin, N + 1)])
+    assert len(ords) == total
+    say(f"full output fp64 N={N} orders {kmin}..{N}")
+    out, _ = api.nplets_measures(Sd, orders=(kmin, N), precision="fp64", out_dtype=torch.float64)
+    om = out[2].cpu().numpy()
+    say(f"reduce fp64 N={N} orders {kmin}..{N} topk=30 bins=24")
+    st = api.nplets_reduce(Sd, orders=(kmin, N), topk=30, hist_bins=24, hist_range=(-40.0, 5.0), precision="fp64")
+    tv, tg, h = st.result()
+    check_lists(tv[0], tg[0], om, ords, 30, 0.0)
+    for k in range(kmin, N + 1):
+        assert np.array_equal(h[0, k], orc.histogram(om[ords == k], -40.0, 5.0, 24)), k
 
 
 def test_reduce_refined_values_enter(env):
