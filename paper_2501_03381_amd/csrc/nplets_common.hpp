@@ -258,19 +258,13 @@ struct FactorOut {
 
 constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
+// packed lower triangle of an order-K matrix (at least one slot)
+template <int K> constexpr int kTri = K * (K + 1) / 2 > 0 ? K * (K + 1) / 2 : 1;
+
+// Factor the packed lower triangle a of R_S (unit diagonal) in registers.
 template <typename F, int K>
-__device__ __forceinline__ FactorOut<F> lane_factor(const int (&c)[K > 0 ? K : 1], const F* __restrict__ sR, int N)
+__device__ __forceinline__ FactorOut<F> lane_factor_tri(F (&a)[kTri<K>])
 {
-    constexpr int NT = K * (K + 1) / 2;
-    F a[NT > 0 ? NT : 1];
-    // gather the strict lower triangle of R_S; the diagonal is 1
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-        const F* row = sR + c[i] * N;
-#pragma unroll
-        for (int j = 0; j < i; ++j) a[tri(i, j)] = row[c[j]];
-        a[tri(i, i)] = F(1);
-    }
     LogProd<F> det;
     bool ok = true;
     // right-looking Cholesky, L overwrites the strict lower triangle and the diagonal slot j
@@ -319,6 +313,22 @@ __device__ __forceinline__ FactorOut<F> lane_factor(const int (&c)[K > 0 ? K : 1
     o.vmax = vmax;
     o.ok = ok;
     return o;
+}
+
+// Gather R_S of the index set c from the staged correlation matrix sR and factor it.
+template <typename F, int K>
+__device__ __forceinline__ FactorOut<F> lane_factor(const int (&c)[K > 0 ? K : 1], const F* __restrict__ sR, int N)
+{
+    F a[kTri<K>];
+    // the strict lower triangle of R_S; the diagonal is 1
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const F* row = sR + c[i] * N;
+#pragma unroll
+        for (int j = 0; j < i; ++j) a[tri(i, j)] = row[c[j]];
+        a[tri(i, i)] = F(1);
+    }
+    return lane_factor_tri<F, K>(a);
 }
 
 // ------------------------------------------------------------------------------------------------

@@ -647,7 +647,7 @@ thoi_status launch_eval(const double* Sigma, int64_t D, int32_t N, const thoi_np
             }
         }
         // every queued n-plet comes from an FP32 lane class (order <= 24)
-        pair_refine_launch(sel->mode, a, ro, red, 1024, s);
+        refine_launch(sel->mode, a, ro, red, s);
     }
     if (reduce && red.topk > 0)
         hipLaunchKernelGGL(k_red_final, dim3((unsigned)(kmax + 1), (unsigned)D), dim3(256), 0, s, red, a.hdr);

@@ -315,17 +315,41 @@ __global__ __launch_bounds__(256) void k_red_final(RedArgs red, WsHeader* hdr)
     }
     if (threadIdx.x == 0) { S.cur[0] = S.cur[1] = 0; }
     __syncthreads();
+    // Segments in batches of one per thread: each thread tests its segment's two list heads
+    // against the current K-th entries, the candidates are compacted, and only those are merged
+    // (tested again against the threshold as it tightens).  After the first batches almost no
+    // segment beats the running lists, so a batch costs one round of parallel loads.
+    __shared__ uint32_t cand[2][256];
+    __shared__ int ncand[2];
     const uint32_t nseg = min(hdr->seg_next, red.seg_cap);
-    for (uint32_t s = 0; s < nseg; ++s) {
-        const SegHdr h = red.seg_hdr[s];
-        if (h.d != d || h.k != k) continue;          // uniform
-        for (int l = 0; l < 2; ++l) {
-            const uint64_t* bk = red.seg_key + ((int64_t)s * 2 + l) * K;
-            const int64_t* bg = red.seg_g + ((int64_t)s * 2 + l) * K;
-            const int c = S.cur[l];
-            if (!red_less(bk[0], bg[0], S.key[l][c][K - 1], S.g[l][c][K - 1])) continue;   // uniform
-            red_merge_sorted(S, l, K, bk, bg, K);
+    for (uint32_t s0 = 0; s0 < nseg; s0 += blockDim.x) {
+        if (threadIdx.x < 2) ncand[threadIdx.x] = 0;
+        __syncthreads();
+        const uint32_t s = s0 + threadIdx.x;
+        if (s < nseg) {
+            const SegHdr h = red.seg_hdr[s];
+            if (h.d == d && h.k == k) {
+                for (int l = 0; l < 2; ++l) {
+                    const int64_t e = ((int64_t)s * 2 + l) * K;
+                    const int c = S.cur[l];
+                    if (red_less(red.seg_key[e], red.seg_g[e], S.key[l][c][K - 1], S.g[l][c][K - 1]))
+                        cand[l][atomicAdd(&ncand[l], 1)] = s;
+                }
+            }
         }
+        __syncthreads();
+        for (int l = 0; l < 2; ++l) {
+            const int nc = ncand[l];
+            for (int j = 0; j < nc; ++j) {
+                const int64_t e = ((int64_t)cand[l][j] * 2 + l) * K;
+                const uint64_t* bk = red.seg_key + e;
+                const int64_t* bg = red.seg_g + e;
+                const int c = S.cur[l];
+                if (!red_less(bk[0], bg[0], S.key[l][c][K - 1], S.g[l][c][K - 1])) continue;   // uniform
+                red_merge_sorted(S, l, K, bk, bg, K);
+            }
+        }
+        __syncthreads();                         // every thread has read ncand before the reset
     }
     const uint32_t nlate = min(hdr->late_next, red.late_cap);
     for (uint32_t b0 = 0; b0 < nlate; b0 += blockDim.x) {

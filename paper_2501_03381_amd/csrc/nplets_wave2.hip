@@ -58,24 +58,36 @@ __device__ __forceinline__ FactorOut<double> pair_factor(const double* __restric
     double r[kW2Max];
     double si = 1.0;
     if constexpr (GLOBAL) {
+        // lane i scales its row by 1/sqrt(Sigma_ii) and publishes the factor for the columns
         const double di = sR[(int64_t)ci * N + ci];
         si = di > 0.0 ? 1.0 / sqrt(di) : __builtin_nan("");
+        wrow[i] = si;
+        wave_sync();
     }
-    // every loop below is unrolled by sfor, so r[] is indexed by constants only
+    // Gather: every load of a group of four columns is issued before any is used (an unused
+    // lane reads a valid entry and discards it); r[] is indexed by constants only.
     sfor<0, kW2Max>([&](auto M) {
         constexpr int m = M;
-        double v = 0.0;
-        if (m < k && m < i && mine) {
-            const int cm = cidx[m];
-            if constexpr (GLOBAL) {
-                const double dm = sR[(int64_t)cm * N + cm];
-                v = sR[(int64_t)ci * N + cm] * si * (dm > 0.0 ? 1.0 / sqrt(dm) : __builtin_nan(""));
-            } else {
-                v = sR[ci * N + cm];
-            }
-        }
-        r[m] = (m == i && mine) ? 1.0 : v;
+        r[m] = (m == i && mine) ? 1.0 : 0.0;
     });
+    sfor<0, kW2Max / 4>([&](auto G) {
+        constexpr int g = G;
+        if (4 * g < k) {
+            double e[4];
+            sfor<0, 4>([&](auto U) {
+                constexpr int u = U;
+                const int cm = 4 * g + u < kh ? cidx[4 * g + u] : 0;
+                if constexpr (GLOBAL) e[u] = sR[(int64_t)ci * N + cm];
+                else e[u] = sR[ci * N + cm];
+            });
+            sfor<0, 4>([&](auto U) {
+                constexpr int u = U, m = 4 * g + u;
+                if constexpr (GLOBAL) e[u] *= si * wrow[m];
+                if (m < i && mine) r[m] = e[u];
+            });
+        }
+    });
+    if constexpr (GLOBAL) wave_sync();          // wrow is reused below
     // Right-looking Cholesky.  Lane i's entries r[m] with m > i, and every entry of a lane beyond
     // the order, are never read for the result; the updates below run on them too, so that the
     // inner loops need no per-lane condition (column entries beyond the order are stale but in
@@ -299,87 +311,270 @@ __global__ __launch_bounds__(kPairThreads) void k_eval_pair(EvalArgs a, PieceTab
     if constexpr (RED) red_end(S, red, a.hdr, d, k);
 }
 
-// FP64 re-evaluation of the n-plets queued by the FP32 lane engine, two per wavefront (each half
-// its own queue entry, order and dataset; entries read from Sigma in global memory).  grid (G),
-// block 64, grid-stride over pairs of queue entries; the queue is complete (the class kernels ran
-// before this one) and a workgroup with no entry leaves at once.
+// ------------------------------------------------------------------------------------------------
+// Refinement: FP64 re-evaluation of the n-plets queued by the FP32 lane engine.
+// ------------------------------------------------------------------------------------------------
+constexpr int kRefineThreads = 256;
+// Largest order refined one per lane (a register triangle of order 18 would spill); orders above
+// go to the pair factoriser.  Lanes factor at order 8 (orders up to 8), 14 (9..14) or 16 (15, 16).
+constexpr int kRefineLaneMax = 16;
+constexpr int kRefineStageMaxN = 64;   // largest N whose correlation matrix is staged in LDS
+
+// Order of queued n-plet `pos` and, in RANGE mode, its rank inside that order.
 template <int MODE>
-__global__ __launch_bounds__(64) void k_refine_pair(EvalArgs a, RangeOrders ro, RedArgs red)
+__device__ __forceinline__ int queued_order(const EvalArgs& a, const RangeOrders& ro, int64_t pos, uint64_t& rank)
 {
-    __shared__ double scol[2 * 2 * kW2Max];
-    __shared__ double swrow[2 * 2 * kW2Max];
-    __shared__ int cidx[2 * kW2Max];
-    __shared__ int sk[2];
-    const int N = a.N;
-    const uint32_t n = min(a.hdr->refine_count, a.refine_cap);
-    const int h = threadIdx.x >> 5, i = threadIdx.x & 31;
-    int* ch = cidx + h * kW2Max;
-    double* col = scol + h * 2 * kW2Max;
-    double* wrow = swrow + h * 2 * kW2Max;
+    int k = 0;
+    rank = 0;
+    if constexpr (MODE == THOI_SEL_RANGE) {
+        const int64_t g = ro.g_begin + pos;
+        k = ro.kmin;
+        while (k < ro.kmax && g >= ro.ostart[k + 1]) ++k;
+        rank = (uint64_t)(g - ro.ostart[k]);
+    } else if constexpr (MODE == THOI_SEL_LIST) {
+        const int32_t* row = a.idx + pos * a.kmax_list;
+        while (k < a.kmax_list && row[k] >= 0) ++k;
+    } else {
+        k = __builtin_popcountll(a.mask[pos]);
+    }
+    return k;
+}
+
+// Store the FP64 result of queued entry o (dataset d, position pos) over its FP32 one.
+__device__ __forceinline__ void refine_store(const EvalArgs& a, const RangeOrders& ro, const RedArgs& red, int mode,
+                                             int64_t o, int d, int64_t pos, int k, const FactorOut<double>& f,
+                                             double sumlogd)
+{
+    EvalArgs b = a;
+    b.precision = THOI_FP64;
+    b.flags = nullptr;
     const bool reduce = red.active != 0;
-    for (uint32_t q0 = 2 * blockIdx.x; q0 < n; q0 += 2 * gridDim.x) {
-        const uint32_t q = q0 + h;
-        const bool act = q < n;
-        int64_t o = 0, pos = 0;
-        int d = 0;
-        if (act) {
-            o = a.refine_list[q];
-            d = (int)(o / a.B);
-            pos = o - (int64_t)d * a.B;
+    double dtc, ddtc, eta, om = 0.0;
+    bias_for(a.bias, k, dtc, ddtc, eta);
+    const bool ok = store_result<double>(b, reduce, d, pos, k, f, sumlogd, dtc, ddtc, eta, true, om);
+    if (a.flags) a.flags[o] = (uint8_t)(THOI_NPLET_REFINED | (ok ? 0 : THOI_NPLET_NOT_PD));
+    if (reduce && ok) red_late(red, a.hdr, d, k, mode == THOI_SEL_RANGE ? ro.g_begin + pos : pos, om);
+}
+
+// One lane, runtime order k <= KP: the n-plet's entries are gathered from Sigma of its own
+// dataset, scaled to correlations, and factored in registers as the order-KP matrix
+// diag(R_S, I).  The identity block adds pivots 1 and inverse-diagonal entries 1, so log det,
+// sum log a_j and max a_j (>= 1 for a correlation matrix) are those of R_S, and the operations on
+// R_S's own entries are the same as at order k.  One code body per KP serves every order (code
+// per order would not fit the instruction cache when the wavefronts of a CU refine different
+// orders).
+template <int MODE, int KP, bool STAGED>
+__device__ __forceinline__ void refine_lane(const EvalArgs& a, const RangeOrders& ro, const RedArgs& red, int64_t o,
+                                            int d, int64_t pos, int k, uint64_t rank, const uint64_t* sBin,
+                                            const double* sR, const double* sLogd)
+{
+    const int N = a.N;
+    uint64_t mask = 0;
+    int c[KP];
+    if constexpr (MODE == THOI_SEL_RANGE) {
+        // lexicographic unranking into a bit mask: take x while the rank is below C(N-1-x, m)
+        int m = k - 1;
+        for (int x = 0; x < N && m >= 0; ++x) {
+            const uint64_t b = sBin[(N - 1 - x) * kW2Max + m];
+            if (rank < b) { mask |= 1ull << x; --m; }
+            else rank -= b;
         }
-        if (i == 0) {
-            int k = 0;
-            if (act) {
+    } else if constexpr (MODE == THOI_SEL_MASK) {
+        mask = a.mask[pos];
+    }
+    if constexpr (MODE == THOI_SEL_LIST) {
+        const int32_t* row = a.idx + pos * a.kmax_list;
+#pragma unroll
+        for (int i = 0; i < KP; ++i) c[i] = i < k ? row[i] : 0;
+    } else {
+#pragma unroll
+        for (int i = 0; i < KP; ++i) {
+            c[i] = i < k ? __builtin_ctzll(mask) : 0;
+            mask &= mask - 1;
+        }
+    }
+    double sumlogd = 0.0;
+    double t[kTri<KP>];
+    if constexpr (STAGED) {
+        // the dataset's correlation matrix and log variances are staged in LDS
+#pragma unroll
+        for (int i = 0; i < KP; ++i) {
+            if (a.write_H && i < k) sumlogd += sLogd[c[i]];
+#pragma unroll
+            for (int j = 0; j < i; ++j) t[tri(i, j)] = i < k ? sR[c[i] * N + c[j]] : 0.0;
+            t[tri(i, i)] = 1.0;
+        }
+    } else {
+        const double* Sg = a.Sigma + (int64_t)d * N * N;
+        double sd[KP];
+#pragma unroll
+        for (int i = 0; i < KP; ++i) {
+            sd[i] = 1.0;
+            if (i < k) {
+                const double di = Sg[(int64_t)c[i] * N + c[i]];
+                sd[i] = di > 0.0 ? 1.0 / sqrt(di) : __builtin_nan("");
+                if (a.write_H) sumlogd += log(di);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < KP; ++i) {
+#pragma unroll
+            for (int j = 0; j < i; ++j) t[tri(i, j)] = i < k ? Sg[(int64_t)c[i] * N + c[j]] * sd[i] * sd[j] : 0.0;
+            t[tri(i, i)] = 1.0;
+        }
+    }
+    const FactorOut<double> f = lane_factor_tri<double, KP>(t);
+    refine_store(a, ro, red, MODE, o, d, pos, k, f, sumlogd);
+}
+
+// grid (G), block kRefineThreads.  Round j gives thread t of workgroup b the queue entry
+// j G T + t G + b (T threads per workgroup): consecutive entries (appended together, usually of
+// one order) go to different workgroups.  The workgroup sorts its entries in LDS by the padded
+// order that factors them, so that each wavefront mostly runs one code body; entries of order
+// above kRefineLaneMax are then dealt round-robin to the wavefronts, two per wavefront at a time.
+// The queue is complete (the class kernels ran before this one).
+template <int MODE>
+__global__ __launch_bounds__(kRefineThreads) void k_refine(EvalArgs a, RangeOrders ro, RedArgs red)
+{
+    constexpr int kWaves = kRefineThreads / 64;
+    __shared__ uint64_t sBin[64 * kW2Max];   // C(n, m), n < N, m < 32 (RANGE)
+    __shared__ int64_t sOst[THOI_MAX_K + 2];
+    __shared__ double scol[kPairHalves * 2 * kW2Max];
+    __shared__ double swrow[kPairHalves * 2 * kW2Max];
+    __shared__ int scidx[kPairHalves * kW2Max];
+    __shared__ int64_t eo[kRefineThreads];    // sorted entries: queue value, rank, order
+    __shared__ uint64_t erank[kRefineThreads];
+    __shared__ int ek[kRefineThreads];
+    __shared__ int ccount[4], cbase[4];
+    __shared__ int dmin, dmax;
+    extern __shared__ __align__(16) unsigned char smem[];   // correlation matrix [N*N] | 1/sd [N] | log var [N]
+    double* sR = reinterpret_cast<double*>(smem);
+    double* sIsd = sR + a.N * a.N;
+    double* sLogd = sIsd + a.N;
+    const int N = a.N;
+    const int64_t n = (int64_t)min(a.hdr->refine_count, a.refine_cap);
+    const int64_t G = gridDim.x;
+    if ((int64_t)blockIdx.x >= n) return;     // uniform in the workgroup: no entry
+    if constexpr (MODE == THOI_SEL_RANGE) {
+        stage_binomials(N, kW2Max, sBin);
+        for (int t = threadIdx.x; t <= ro.kmax + 1 && t < THOI_MAX_K + 2; t += blockDim.x) sOst[t] = ro.ostart[t];
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int h = lane >> 5, i = lane & 31;
+    int* ch = scidx + (2 * w + h) * kW2Max;
+    double* col = scol + (2 * w + h) * 2 * kW2Max;
+    double* wrow = swrow + (2 * w + h) * 2 * kW2Max;
+    for (int64_t j0 = 0; j0 < n; j0 += G * kRefineThreads) {
+        if (threadIdx.x < 4) ccount[threadIdx.x] = 0;
+        if (threadIdx.x == 0) { dmin = INT32_MAX; dmax = -1; }
+        __syncthreads();
+        // load, classify (0: padded 8, 1: 14, 2: kRefineLaneMax, 3: pair), count
+        const int64_t q = j0 + (int64_t)threadIdx.x * G + blockIdx.x;
+        int64_t o = -1;
+        int k = 0, cls = 0;
+        uint64_t rank = 0;
+        if (q < n) {
+            o = a.refine_list[q];
+            const int d = (int)(o / a.B);
+            const int64_t pos = o - (int64_t)d * a.B;
+            if constexpr (MODE == THOI_SEL_RANGE) {
+                const int64_t g = ro.g_begin + pos;
+                k = ro.kmin;
+                while (k < ro.kmax && g >= sOst[k + 1]) ++k;
+                rank = (uint64_t)(g - sOst[k]);
+            } else {
+                k = queued_order<MODE>(a, ro, pos, rank);
+            }
+            cls = k <= 8 ? 0 : (k <= 14 ? 1 : (k <= kRefineLaneMax ? 2 : 3));
+            atomicMin(&dmin, d);
+            atomicMax(&dmax, d);
+        }
+        const int slot = q < n ? atomicAdd(&ccount[cls], 1) : -1;
+        __syncthreads();
+        // entries of one dataset (always so for a single dataset) and N <= 64: gather from LDS
+        const bool staged = N <= kRefineStageMaxN && dmin == dmax;
+        if (staged) stage_corr<double>(a.Sigma + (int64_t)dmin * N * N, N, sR, sIsd, sLogd);
+        if (threadIdx.x == 0) {
+            cbase[0] = 0;
+            cbase[1] = ccount[0];
+            cbase[2] = cbase[1] + ccount[1];
+            cbase[3] = cbase[2] + ccount[2];
+        }
+        __syncthreads();
+        if (slot >= 0) {
+            const int e = cbase[cls] + slot;
+            eo[e] = o;
+            erank[e] = rank;
+            ek[e] = k;
+        }
+        __syncthreads();
+        const int nlane = cbase[3], npair = ccount[3];
+        // lane path: sorted entry threadIdx.x
+        if ((int)threadIdx.x < nlane) {
+            const int64_t oo = eo[threadIdx.x];
+            const int d = (int)(oo / a.B);
+            const int64_t pos = oo - (int64_t)d * a.B;
+            const int kk = ek[threadIdx.x];
+            const uint64_t rk = erank[threadIdx.x];
+            if (!staged) refine_lane<MODE, kRefineLaneMax, false>(a, ro, red, oo, d, pos, kk, rk, sBin, sR, sLogd);
+            else if (kk <= 8) refine_lane<MODE, 8, true>(a, ro, red, oo, d, pos, kk, rk, sBin, sR, sLogd);
+            else if (kk <= 14) refine_lane<MODE, 14, true>(a, ro, red, oo, d, pos, kk, rk, sBin, sR, sLogd);
+            else refine_lane<MODE, kRefineLaneMax, true>(a, ro, red, oo, d, pos, kk, rk, sBin, sR, sLogd);
+        }
+        // pair path: wavefront w takes pairs w, w + kWaves, ... of the sorted high-order entries
+        for (int p0 = 2 * w; p0 < npair; p0 += 2 * kWaves) {
+            const int e = p0 + h;
+            const bool hact = e < npair;
+            int64_t ho = 0, hpos = 0;
+            int hd = 0, kh = 0;
+            uint64_t hrank = 0;
+            if (hact) {
+                ho = eo[nlane + e];
+                hd = (int)(ho / a.B);
+                hpos = ho - (int64_t)hd * a.B;
+                kh = ek[nlane + e];
+                hrank = erank[nlane + e];
                 if constexpr (MODE == THOI_SEL_RANGE) {
-                    const int64_t g = ro.g_begin + pos;
-                    k = ro.kmin;
-                    while (k < ro.kmax && g >= ro.ostart[k + 1]) ++k;
-                    k = k < kW2Max ? k : kW2Max;   // queued n-plets are of order <= 24
-                    pair_unrank((uint64_t)(g - ro.ostart[k]), N, k, ch);
+                    if (i == 0) unrank_lex_rt(hrank, N, kh, sBin, kW2Max, ch);
                 } else if constexpr (MODE == THOI_SEL_LIST) {
-                    const int32_t* row = a.idx + pos * a.kmax_list;
-                    while (k < a.kmax_list && k < kW2Max && row[k] >= 0) { ch[k] = row[k]; ++k; }
+                    if (i < kh) ch[i] = a.idx[hpos * a.kmax_list + i];
                 } else {
-                    uint64_t m = a.mask[pos];
-                    while (m && k < kW2Max) { ch[k++] = __builtin_ctzll(m); m &= m - 1; }
+                    uint64_t m = a.mask[hpos];
+                    for (int t = 0; t < i && m; ++t) m &= m - 1;
+                    if (i < kh) ch[i] = __builtin_ctzll(m);
                 }
             }
-            sk[h] = k;
-        }
-        __syncthreads();
-        const int kh = sk[h];
-        const int kk = sk[0] > sk[1] ? sk[0] : sk[1];
-        const FactorOut<double> f = pair_factor<true>(a.Sigma + (int64_t)d * N * N, N, ch, kk, kh, col, wrow);
-        double sumlogd = 0.0;
-        if (a.write_H) {
-            const double* Sg = a.Sigma + (int64_t)d * N * N;
-            sumlogd = half_sum(i < kh ? log(Sg[(int64_t)ch[i] * N + ch[i]]) : 0.0);
-        }
-        if (i == 0 && act) {
-            EvalArgs b = a;
-            b.precision = THOI_FP64;
-            b.flags = nullptr;
-            double dtc, ddtc, eta, om = 0.0;
-            bias_for(a.bias, kh, dtc, ddtc, eta);
-            const bool ok = store_result<double>(b, reduce, d, pos, kh, f, sumlogd, dtc, ddtc, eta, true, om);
-            if (a.flags) a.flags[o] = (uint8_t)(THOI_NPLET_REFINED | (ok ? 0 : THOI_NPLET_NOT_PD));
-            if (reduce && ok) {
-                const int64_t g = MODE == THOI_SEL_RANGE ? ro.g_begin + pos : pos;
-                red_late(red, a.hdr, d, kh, g, om);
+            wave_sync();
+            // every shuffle runs with the whole wavefront active (an inactive source lane reads 0)
+            const int k0 = __shfl(kh, 0), k1 = __shfl(kh, 32);
+            const double* Sg = a.Sigma + (int64_t)hd * N * N;
+            double sumlogd = 0.0;
+            FactorOut<double> f;
+            if (staged) {
+                f = pair_factor<false>(sR, N, ch, k0 > k1 ? k0 : k1, kh, col, wrow);
+                if (a.write_H) sumlogd = half_sum(i < kh ? sLogd[ch[i]] : 0.0);
+            } else {
+                f = pair_factor<true>(Sg, N, ch, k0 > k1 ? k0 : k1, kh, col, wrow);
+                if (a.write_H) sumlogd = half_sum(i < kh ? log(Sg[(int64_t)ch[i] * N + ch[i]]) : 0.0);
             }
+            if (i == 0 && hact) refine_store(a, ro, red, MODE, ho, hd, hpos, kh, f, sumlogd);
+            wave_sync();
         }
-        __syncthreads();
+        __syncthreads();                         // the sorted arrays are rewritten next round
     }
 }
 
 }  // namespace
 
-void pair_refine_launch(int mode, const EvalArgs& a, const RangeOrders& ro, const RedArgs& red, unsigned G,
-                        hipStream_t s)
+void refine_launch(int mode, const EvalArgs& a, const RangeOrders& ro, const RedArgs& red, hipStream_t s)
 {
-    if (mode == THOI_SEL_RANGE) hipLaunchKernelGGL(k_refine_pair<THOI_SEL_RANGE>, dim3(G), dim3(64), 0, s, a, ro, red);
-    else if (mode == THOI_SEL_LIST) hipLaunchKernelGGL(k_refine_pair<THOI_SEL_LIST>, dim3(G), dim3(64), 0, s, a, ro, red);
-    else hipLaunchKernelGGL(k_refine_pair<THOI_SEL_MASK>, dim3(G), dim3(64), 0, s, a, ro, red);
+    // enough workgroups for every queue slot to be one thread's, up to four rounds of a full GPU
+    const int64_t need = ((int64_t)a.refine_cap + kRefineThreads - 1) / kRefineThreads;
+    const unsigned G = (unsigned)(need < 1024 ? (need > 0 ? need : 1) : 1024);
+    const size_t lds = a.N <= kRefineStageMaxN ? ((size_t)a.N * a.N + 2 * (size_t)a.N) * sizeof(double) : 0;
+    if (mode == THOI_SEL_RANGE) hipLaunchKernelGGL(k_refine<THOI_SEL_RANGE>, dim3(G), dim3(kRefineThreads), lds, s, a, ro, red);
+    else if (mode == THOI_SEL_LIST) hipLaunchKernelGGL(k_refine<THOI_SEL_LIST>, dim3(G), dim3(kRefineThreads), lds, s, a, ro, red);
+    else hipLaunchKernelGGL(k_refine<THOI_SEL_MASK>, dim3(G), dim3(kRefineThreads), lds, s, a, ro, red);
 }
 
 size_t pair_lds_bytes(int N, bool reduce)

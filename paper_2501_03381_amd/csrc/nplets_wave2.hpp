@@ -17,9 +17,8 @@ size_t pair_lds_bytes(int N, bool reduce);
 void pair_launch(int mode, bool reduce, const EvalArgs& a, const PieceTable& t, const RedArgs& red, int klo, int kmax,
                  int64_t nblk, hipStream_t s);
 
-// FP64 re-evaluation of the refinement queue of a call (two entries per wavefront), replacing the
-// FP32 results of the queued n-plets; every queued n-plet has order <= kW2Max.
-void pair_refine_launch(int mode, const EvalArgs& a, const RangeOrders& ro, const RedArgs& red, unsigned G,
-                        hipStream_t s);
+// FP64 re-evaluation of the refinement queue of a call, replacing the FP32 results of the queued
+// n-plets (orders up to 16 one per lane, the others up to kW2Max two per wavefront).
+void refine_launch(int mode, const EvalArgs& a, const RangeOrders& ro, const RedArgs& red, hipStream_t s);
 
 }  // namespace thoi

@@ -298,8 +298,9 @@ def test_pair_and_wave_engines_split_at_32(env):
 
 
 def test_refinement_pairs_mixed_orders_and_datasets(env):
-    """The FP64 re-evaluation takes two queued n-plets per wavefront, which may differ in order
-    and dataset: near-duplicate columns in two datasets, LIST rows of orders 3..24."""
+    """The FP64 re-evaluation of queued n-plets: one per lane up to order 14, above that two per
+    wavefront, and the two may differ in order and dataset.  Near-duplicate columns in two
+    datasets; LIST rows and MASK words of orders 3..24, and a RANGE window over orders 14..17."""
     torch, api, B, synth, orc = env
     rng = np.random.default_rng(17)
     Ss = []
@@ -325,6 +326,32 @@ def test_refinement_pairs_mixed_orders_and_datasets(env):
         ref, _, _ = orc.eval_list(S[d], idx)
         for m in range(4):
             assert_close(out[m, d], ref[m], TOL32, f"d={d} m={m}")
+    # the same rows as 64-bit masks, and a RANGE window over orders 12..17 of 22 variables
+    masks = np.array([sum(1 << int(j) for j in r) for r in rows], dtype=np.uint64).astype(np.int64)
+    say("MASK fp32_refine D=2 N=40 orders 3..24 with near-duplicate columns")
+    outm, flm = api.nplets_measures(dev(torch, S), masks=dev(torch, masks), precision="fp32_refine",
+                                    out_dtype=torch.float64)
+    outm, flm = host(outm), host(flm)
+    assert np.array_equal(flm, flags)
+    for d in range(2):
+        ref, _, _ = orc.eval_list(S[d], idx)
+        for m in range(4):
+            assert_close(outm[m, d], ref[m], TOL32, f"MASK d={d} m={m}")
+    S22 = S[0][:22, :22].copy()
+    g0 = B.thoi_count(22, 3, 13)
+    cnt = B.thoi_count(22, 14, 17)
+    say(f"RANGE fp32_refine N=22 window of {cnt} n-plets in orders 14..17")
+    outr, flr = api.nplets_measures(dev(torch, S22), orders=(3, 17), g_range=(g0, cnt), precision="fp32_refine",
+                                    out_dtype=torch.float64)
+    outr, flr = host(outr), host(flr)
+    refined = np.nonzero(flr & B.THOI_NPLET_REFINED)[0]
+    assert len(refined) > 1000
+    pick = np.unique(np.concatenate([refined[:: max(1, len(refined) // 1500)], rng.integers(0, cnt, 500)]))
+    rws = orc.pad_list([lex_unrank(int(g0 + p), 22, 3) for p in pick], kmax=22)
+    assert set(int((r >= 0).sum()) for r in rws[np.isin(pick, refined)]) >= {14, 15, 16, 17}
+    ref, _, _ = orc.eval_list(S22, rws)
+    for m in range(4):
+        assert_close(outr[m, pick], ref[m], TOL32, f"RANGE m={m}")
 
 
 # ------------------------------------------------------------------------------------------------ LIST / MASK
