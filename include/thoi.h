@@ -251,8 +251,10 @@ thoi_status thoi_nplets_eval_backward(const double* Sigma, int64_t D, int32_t N,
  *   device [total] or NULL.  With opts->reduce the reducer arrays are [D][kmax+1]... as in
  *   thoi_nplets_eval and g is the index inside dataset d.
  *   kmax must not exceed the register-resident orders (24 in FP32, 18 in FP64).
- * Work runs as one persistent launch per register class over a (dataset, order, tile) table
- * that a planning kernel builds in the workspace; datasets are processed in chunks of 256.
+ * The sizes travel to the device in kernel arguments (512 datasets per small upload launch); one
+ * planning kernel derives the per-dataset offsets and work-unit tables in the workspace; then one
+ * persistent launch per register class covers every dataset, each workgroup walking a contiguous
+ * range of (dataset, order, tile) units.
  */
 thoi_status thoi_nplets_eval_multi(const double* Sigma, const int32_t* N_d, const int32_t* T_d, int64_t D,
                                    int32_t kmin, int32_t kmax, const thoi_eval_opts* opts, void* out,
