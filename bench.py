@@ -57,6 +57,37 @@ def flops(k: int) -> int:
     return 2 * (k ** 3 - k) // 3 + k * (k + 1)
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (for the CPU baseline records)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def lex_unrank(g: int, N: int, kmin: int) -> tuple:
+    """The n-plet at global index g of the enumeration of orders kmin.. of N variables (orders
+    ascending, each in lexicographic order), with exact integer binomials."""
+    k = kmin
+    while g >= math.comb(N, k):
+        g -= math.comb(N, k)
+        k += 1
+    out, x = [], 0
+    for i in range(k):
+        m = k - 1 - i
+        while g >= math.comb(N - 1 - x, m):
+            g -= math.comb(N - 1 - x, m)
+            x += 1
+        out.append(x)
+        x += 1
+    return tuple(out)
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -69,7 +100,7 @@ def parse():
     p.add_argument("--no-saturated", action="store_true", help="skip the 64-replica saturation run")
     p.add_argument("--workload", default="latent20",
                    choices=["latent20", "ar1_30", "uneven1024", "latent100_grad", "classes", "greedy100", "anneal100",
-                            "paired64"],
+                            "paired64", "refine20"],
                    help="latent20: the headline N=20 step (default); the others time the remaining "
                         "configurations of the method (one JSON line each)")
     p.add_argument("--profile-kernels", action="store_true",
@@ -281,9 +312,27 @@ def bench_ar1_30(torch, np, api, B, synth, dev, args):
             eng[f"{prec} {engine}"] = {"seconds": best, "nplets_per_s": n712 / best, "flops": fl,
                                        "tflops": round(ach, 3), "frac_of_78.6": round(ach / 78.6, 4)}
     res["orders_7_12_engines"] = eng
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        Sh = oracle.gc_covariance(synth.ar1_30())
+        ns = 100000
+        gs = np.sort(np.random.default_rng(30).choice(total, ns, replace=False))
+        rows = oracle.pad_list([lex_unrank(int(g), N, kmin) for g in gs], kmax=kmax)
+        t0 = time.perf_counter()
+        oracle.eval_list(Sh, rows)
+        dt = time.perf_counter() - t0
+        cpu = {"value": ns / dt, "unit": "n-plets/s", "cores": oracle.max_threads(0), "kind": "oracle",
+               "cpu_model": cpu_model(),
+               "sample": f"{ns} seeded uniform n-plets of the {total:,} (all orders 3..30), measures only, "
+                         f"{dt:.2f} s; FP64, one LU per joint and per leave-one-out determinant",
+               "extrapolated_full_seconds": total / (ns / dt),
+               "extrapolation": "the sample's rate applied to every n-plet of the enumeration (not measured)"}
     return {"workload": "ar1_30: N=30, T=1200, seed 2, all orders 3..30 (1,073,741,358 n-plets), streaming "
                         "top-100/bottom-100 + 256-bin histogram per order", "metric": "n-plets/s",
-            "value": res["fp32_refine"]["nplets_per_s"], "unit": "n-plets/s", "nplets": total, "detail": res}
+            "value": res["fp32_refine"]["nplets_per_s"], "unit": "n-plets/s", "nplets": total, "detail": res,
+            "cpu_baseline": cpu}
 
 
 def bench_uneven(torch, np, api, B, synth, dev, args):
@@ -297,10 +346,25 @@ def bench_uneven(torch, np, api, B, synth, dev, args):
     t = tune.tune_multi(flat, Ns, 3, 5, use_cache=False)
     ev = api.MultiEvaluator(Ns, 3, 5, dev, "fp32_refine", seg_tiles=t["seg_tiles"], grid_blocks=t["grid_blocks"])
     ms = kernel_ms(torch, lambda st: ev(flat, stream=st.value), reps=10)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        small = [X for X in Xs if X.shape[1] <= 20]
+        n = 0
+        t0 = time.perf_counter()
+        for X in small:
+            oracle.eval_range(oracle.gc_covariance(X), 3, 5)
+            n += oracle.count_nplets(X.shape[1], 3, 5)
+        dt = time.perf_counter() - t0
+        cpu = {"value": n / dt, "unit": "n-plets/s", "cores": oracle.max_threads(0), "kind": "oracle",
+               "cpu_model": cpu_model(),
+               "sample": f"the {len(small)} datasets with N <= 20: copula + covariance + all n-plets of orders "
+                         f"3..5 ({n:,} n-plets), {dt:.1f} s; FP64"}
     return {"workload": "uneven1024: 1024 datasets, N~U{10..40}, T~U{500..5000}, seed 3, orders 3..5",
             "metric": "n-plets/s", "value": ev.total / (ms * 1e-3), "unit": "n-plets/s", "nplets": ev.total,
             "ms_per_call": ms, "tuned": {"seg_tiles": t["seg_tiles"], "grid_blocks": t["grid_blocks"]},
-            "status": ev.status()}
+            "status": ev.status(), "cpu_baseline": cpu}
 
 
 def bench_greedy(torch, np, api, B, synth, dev, args):
@@ -339,6 +403,7 @@ def bench_greedy(torch, np, api, B, synth, dev, args):
         n = math.comb(100, 3) + sum(len({tuple(sorted(s + (v,))) for s in ref[k - 1][0] for v in range(100)
                                          if v not in s}) for k in range(4, 21))
         cpu = {"value": n / dt, "unit": "n-plets/s", "cores": oracle.max_threads(0), "kind": "oracle",
+               "cpu_model": cpu_model(),
                "sample": f"oracle greedy, orders 3..20, kappa 16, maximise: {n} n-plets in {dt:.1f} s",
                "order20_omega": float(ref[20][1][0])}
     return {"workload": "greedy100: concatenated PGM (weak/strong R, weak/strong S, 20 independent), "
@@ -380,6 +445,7 @@ def bench_anneal(torch, np, api, B, synth, dev, args):
         osearch.anneal(S, m0[:64], {k: v[:30, :64] for k, v in dr.items()}, T0=0.2, alpha=0.99)
         dt = time.perf_counter() - t0
         cpu = {"value": 64 * 31 / dt, "unit": "n-plets/s", "cores": oracle.max_threads(0), "kind": "oracle",
+               "cpu_model": cpu_model(),
                "sample": f"oracle annealer, 64 chains x 30 iterations, order 20: {64 * 31} n-plets in {dt:.2f} s"}
     return {"workload": "anneal100: concatenated PGM, order 20, 1024 chains x 800 iterations, FP64",
             "metric": "n-plets/s", "value": res["max"]["nplets_per_s"], "unit": "n-plets/s", "detail": res,
@@ -427,6 +493,7 @@ def bench_paired(torch, np, api, B, synth, dev, args):
         dt = time.perf_counter() - t0
         cpu = {"value": D * len(idx) / dt, "unit": "n-plet x dataset evaluations/s", "cores": oracle.max_threads(0),
                "kind": "oracle", "sample": f"all {len(idx)} triplets x {D} datasets + paired effect, {dt:.2f} s",
+               "cpu_model": cpu_model(),
                "best_triplet": [int(x) for x in idx[int(np.nanargmin(ref))] if x >= 0]}
     return {"workload": "paired64: 32 subjects x 2 conditions, N=20, T=2000, planted synergistic triplet (2, 5, 9); "
                         "orders 3..6 against 64 covariance matrices, paired effect size of Omega",
@@ -458,13 +525,74 @@ def bench_grad(torch, np, api, B, synth, dev, args):
     kk = (idx >= 0).sum(axis=1).astype(np.int64)
     fl = int(adjoint_flops(kk).sum())
     ach = fl / (bwd * 1e-3) / 1e12
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        Sh = oracle.gc_covariance(X)
+        t0 = time.perf_counter()
+        oracle.eval_list(Sh, idx)
+        t_fwd = time.perf_counter() - t0
+        # central differences (h = 1e-6) of the literal measures of 100 seeded n-plets: one pair of
+        # single-n-plet evaluations per entry of the n-plet's symmetric block
+        pick = np.random.default_rng(100).choice(idx.shape[0], 100, replace=False)
+        threads = oracle.max_threads(0)
+        h, evals = 1e-6, 0
+        t0 = time.perf_counter()
+        for b in pick:
+            r = idx[b][idx[b] >= 0]
+            k = len(r)
+            sub = np.ascontiguousarray(Sh[np.ix_(r, r)])
+            loc = np.arange(k, dtype=np.int32)[None, :]
+            for i in range(k):
+                for j in range(i, k):
+                    P, M = sub.copy(), sub.copy()
+                    P[i, j] += h
+                    M[i, j] -= h
+                    if i != j:
+                        P[j, i] += h
+                        M[j, i] -= h
+                    oracle.eval_list(P, loc, nthreads=1)
+                    oracle.eval_list(M, loc, nthreads=1)
+                    evals += 2
+        t_fd = time.perf_counter() - t0
+        oracle.max_threads(threads)              # the single-thread calls set the OpenMP default
+        cpu = {"value": idx.shape[0] / t_fwd, "unit": "n-plets/s", "cores": threads, "kind": "oracle",
+               "cpu_model": cpu_model(),
+               "sample": f"forward: all {idx.shape[0]:,} n-plets, {t_fwd:.2f} s (FP64, LU per determinant)",
+               "fd_100": {"seconds": t_fd, "single_nplet_evaluations": evals, "cores": 1,
+                          "sample": "central differences, h = 1e-6, of the measures of 100 seeded n-plets "
+                                    "with respect to their covariance entries"}}
     return {"workload": "latent100_grad: N=100, T=2000, seed 4, 1e5 n-plets of order 8..20", "metric": "n-plets/s",
             "value": idx.shape[0] / (fwd * 1e-3), "unit": "n-plets/s", "forward_ms": fwd, "backward_ms": bwd,
             "backward_nplets_per_s": idx.shape[0] / (bwd * 1e-3),
             "backward_roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": 78.6, "unit": "TFLOP/s",
                                   "frac": round(ach / 78.6, 4), "flops_per_call": fl,
                                   "note": "whole adjoint call (bucketing + lane classes); peak = FP64 vector, "
-                                          "also the non-packed FP32 rate"}}
+                                          "also the non-packed FP32 rate"},
+            "cpu_baseline": cpu}
+
+
+def bench_refine20(torch, np, api, B, synth, dev, args):
+    """latent_20 with one near-duplicate column (x_1 = x_0 + 1e-4 noise, seed 3): every n-plet holding
+    both is ill-conditioned (2^18 of them), so the FP32 pass queues it for FP64 re-evaluation.  The
+    evaluation of all orders 3..20 with FP32 + refinement against plain FP64, each timed as a graph
+    of repeated calls on a resident Sigma."""
+    X = synth.latent_20()
+    X[:, 1] = X[:, 0] + 1e-4 * np.random.default_rng(3).standard_normal(X.shape[0])
+    S = api.gc_covariance(torch.from_numpy(X).to(dev))
+    N, total = 20, B.thoi_count(20, 3, 20)
+    res = {}
+    for prec in ("fp32_refine", "fp64", "fp32"):
+        odt = torch.float64 if prec == "fp64" else torch.float32
+        ev = api.Evaluator(1, N, api.range_selection(N, 3, 20), api.make_opts(prec, odt), dev, odt)
+        ms = kernel_ms(torch, lambda st: ev(S, stream=st.value), reps=50)
+        res[prec] = {"ms": ms, "nplets_per_s": total / (ms * 1e-3),
+                     "refined_nplets": ev.refine_count() if prec == "fp32_refine" else 0}
+    return {"workload": "refine20: latent_20 with a near-duplicate column (x_1 = x_0 + 1e-4 N(0,1), seed 3), all "
+                        "orders 3..20 (1,048,365 n-plets)", "metric": "n-plets/s",
+            "value": res["fp32_refine"]["nplets_per_s"], "unit": "n-plets/s", "detail": res,
+            "fp32_refine_over_fp64_time": res["fp32_refine"]["ms"] / res["fp64"]["ms"]}
 
 
 def bench_classes(torch, np, api, B, synth, dev, args):
@@ -511,7 +639,7 @@ def main():
     if args.workload != "latent20":
         extra = {"ar1_30": bench_ar1_30, "uneven1024": bench_uneven, "latent100_grad": bench_grad,
                  "classes": bench_classes, "greedy100": bench_greedy, "anneal100": bench_anneal,
-                 "paired64": bench_paired}[args.workload]
+                 "paired64": bench_paired, "refine20": bench_refine20}[args.workload]
         print(json.dumps(extra(torch, np, api, B, synth, dev, args)), flush=True)
         return
 
@@ -647,8 +775,18 @@ def main():
             ref, _, _ = oracle.eval_list(oracle.gc_covariance(Xh), idx_all[pick])
             dt = time.perf_counter() - t0
             sample = f"copula + covariance, then {n_s} seeded uniform n-plets of the {total:,}, {dt:.1f} s"
+        # the same oracle on one thread, over about a fifth of the time budget
+        n1 = int(min(total, max(500, rate_pilot / max(threads, 1) * args.cpu_seconds / 5)))
+        pick1 = np.sort(rng.choice(total, n1, replace=False))
+        t0 = time.perf_counter()
+        oracle.eval_list(Sig_c, idx_all[pick1], nthreads=1)
+        dt1 = time.perf_counter() - t0
+        oracle.max_threads(threads)              # the single-thread call set the OpenMP default
         cpu = {"value": n_s / dt, "unit": "n-plets/s", "cores": threads, "kind": "oracle",
-               "sample": sample + "; FP64, one LU per joint and per leave-one-out determinant"}
+               "cpu_model": cpu_model(),
+               "sample": sample + "; FP64, one LU per joint and per leave-one-out determinant",
+               "single_thread": {"value": n1 / dt1, "unit": "n-plets/s", "cores": 1,
+                                 "sample": f"{n1} seeded uniform n-plets of the {total:,} (measures only), {dt1:.1f} s"}}
         err = np.abs(out32[:, pick] - ref)
         parity = {"n_checked": int(len(pick)), "max_abs_err": {m: float(np.nanmax(err[i])) for i, m in
                                                     enumerate(("TC", "DTC", "Omega", "S"))},

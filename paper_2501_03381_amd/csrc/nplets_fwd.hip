@@ -57,7 +57,7 @@ __global__ __launch_bounds__(kTile) void k_eval_lane(EvalArgs a, PieceTable tab,
     double* sIsd = reinterpret_cast<double*>(smem + off);
     double* sLogd = sIsd + N;
     uint64_t* sBin = reinterpret_cast<uint64_t*>(sLogd + N);
-    RedLds& Rl = *reinterpret_cast<RedLds*>(smem + lane_stage_bytes(N, kb, sizeof(F)));
+    RedLds Rl = red_view(smem + lane_stage_bytes(N, kb, sizeof(F)), red.topk, red.bins);
     if (threadIdx.x == 0) bias_for(a.bias, k, sbias[0], sbias[1], sbias[2]);
     stage_corr<F>(a.Sigma + (int64_t)d * N * N, N, sR, sIsd, sLogd, MODE == THOI_SEL_RANGE ? sBin : nullptr, kb);
     constexpr bool reduce = RED;
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(64) void k_eval_wave(EvalArgs a, PieceTable tab, Re
     double* res_v = reinterpret_cast<double*>(cidx + 64);
     int64_t* res_g = reinterpret_cast<int64_t*>(res_v + 64);
     int* res_ok = reinterpret_cast<int*>(res_g + 64);
-    RedLds& S = *reinterpret_cast<RedLds*>(smem + wave_stage_bytes(N, kmax, MODE == THOI_SEL_RANGE));
+    RedLds S = red_view(smem + wave_stage_bytes(N, kmax, MODE == THOI_SEL_RANGE), red.topk, red.bins);
     if (threadIdx.x == 0) bias_for(a.bias, k, sbias[0], sbias[1], sbias[2]);
     if constexpr (MODE == THOI_SEL_RANGE) stage_binomials(N, 64, sBin);
     stage_corr<double>(a.Sigma + (int64_t)d * N * N, N, sR, sIsd, sLogd);
@@ -476,7 +476,7 @@ void launch_engines(EvalArgs& a, const Plan& P, const RedArgs& red, hipStream_t 
         const int c = order[oc];
         if (P.nblk[c] == 0) continue;
         const int kb = MODE == THOI_SEL_RANGE ? cls[c].hi : 0;
-        const size_t lds = lane_stage_bytes(N, kb, sizeof(F)) + red_lds(reduce);
+        const size_t lds = lane_stage_bytes(N, kb, sizeof(F)) + red_lds(red);
         const LaneKernel kern = lane_kernel<F, MODE>(c, reduce);
         hipLaunchKernelGGL(kern, dim3((unsigned)P.nblk[c], (unsigned)a.D), dim3(kTile), lds, fan.stream(b++), a,
                            P.tabs[c], red);
@@ -487,7 +487,7 @@ void launch_engines(EvalArgs& a, const Plan& P, const RedArgs& red, hipStream_t 
         pair_launch(MODE, reduce, a, P.wtab, red, lane_max_for(a.precision) + 1, P.wkmax < kW2Max ? P.wkmax : kW2Max,
                     P.wblk, fan.stream(b++));
     if (P.wblk_hi) {
-        const size_t lds = wave_stage_bytes(N, P.wkmax, MODE == THOI_SEL_RANGE) + red_lds(reduce);
+        const size_t lds = wave_stage_bytes(N, P.wkmax, MODE == THOI_SEL_RANGE) + red_lds(red);
         const WaveKernel wk = wave_kernel<MODE>(reduce);
         hipLaunchKernelGGL(wk, dim3((unsigned)P.wblk_hi, (unsigned)a.D), dim3(64), lds, fan.stream(b++), a, P.wtab,
                            red, kW2Max + 1, P.wkmax);
@@ -549,11 +549,11 @@ size_t eval_lds_bytes(int32_t N, const thoi_nplets* sel, const thoi_eval_opts* o
     const int kmax = sel_kmax(sel, N);
     const int fsize = opts->precision == THOI_FP64 ? 8 : 4;
     const int lane_max = lane_max_for(opts->precision);
-    size_t need = lane_stage_bytes(N, range ? kF32LaneMax : 0, fsize) + red_lds(reduce);
+    size_t need = lane_stage_bytes(N, range ? kF32LaneMax : 0, fsize) + red_lds(opts->reduce);
     if (kmax > lane_max) {
-        size_t w = pair_lds_bytes(N, reduce);
+        size_t w = pair_lds_bytes(N, red_lds(opts->reduce));
         if (kmax > kW2Max) {
-            const size_t w2 = wave_stage_bytes(N, kmax, range) + red_lds(reduce);
+            const size_t w2 = wave_stage_bytes(N, kmax, range) + red_lds(opts->reduce);
             w = w > w2 ? w : w2;
         }
         need = need > w ? need : w;

@@ -301,7 +301,8 @@ __host__ __device__ inline size_t wave_stage_bytes(int N, int kmax, bool with_bi
 // ------------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_red_final(RedArgs red, WsHeader* hdr)
 {
-    __shared__ RedLds S;
+    __shared__ __align__(16) unsigned char sred[red_lds_bytes(kRedMaxK, 0)];
+    RedLds S = red_view(sred, red.topk, 0);
     const int k = blockIdx.x, d = blockIdx.y;
     const int K = red.topk;
     if (K <= 0) return;
@@ -310,8 +311,8 @@ __global__ __launch_bounds__(256) void k_red_final(RedArgs red, WsHeader* hdr)
     for (int i = threadIdx.x; i < 2 * K; i += blockDim.x) {
         const int l = i / K, j = i % K;
         const bool has = tg[i] >= 0;
-        S.key[l][0][j] = has ? red_list_key(l, tv[i]) : kKeyEmpty;
-        S.g[l][0][j] = has ? tg[i] : kGEmpty;
+        S.keys(l, 0)[j] = has ? red_list_key(l, tv[i]) : kKeyEmpty;
+        S.gs(l, 0)[j] = has ? tg[i] : kGEmpty;
     }
     if (threadIdx.x == 0) { S.cur[0] = S.cur[1] = 0; }
     __syncthreads();
@@ -332,7 +333,7 @@ __global__ __launch_bounds__(256) void k_red_final(RedArgs red, WsHeader* hdr)
                 for (int l = 0; l < 2; ++l) {
                     const int64_t e = ((int64_t)s * 2 + l) * K;
                     const int c = S.cur[l];
-                    if (red_less(red.seg_key[e], red.seg_g[e], S.key[l][c][K - 1], S.g[l][c][K - 1]))
+                    if (red_less(red.seg_key[e], red.seg_g[e], S.keys(l, c)[K - 1], S.gs(l, c)[K - 1]))
                         cand[l][atomicAdd(&ncand[l], 1)] = s;
                 }
             }
@@ -345,7 +346,7 @@ __global__ __launch_bounds__(256) void k_red_final(RedArgs red, WsHeader* hdr)
                 const uint64_t* bk = red.seg_key + e;
                 const int64_t* bg = red.seg_g + e;
                 const int c = S.cur[l];
-                if (!red_less(bk[0], bg[0], S.key[l][c][K - 1], S.g[l][c][K - 1])) continue;   // uniform
+                if (!red_less(bk[0], bg[0], S.keys(l, c)[K - 1], S.gs(l, c)[K - 1])) continue;   // uniform
                 red_merge_sorted(S, l, K, bk, bg, K);
             }
         }
@@ -369,10 +370,10 @@ __global__ __launch_bounds__(256) void k_red_final(RedArgs red, WsHeader* hdr)
     __syncthreads();
     for (int i = threadIdx.x; i < 2 * K; i += blockDim.x) {
         const int l = i / K, j = i % K;
-        const uint64_t key = S.key[l][S.cur[l]][j];
+        const uint64_t key = S.keys(l, S.cur[l])[j];
         const bool has = key != kKeyEmpty;
         tv[i] = has ? red_list_val(l, key) : __builtin_nan("");
-        tg[i] = has ? S.g[l][S.cur[l]][j] : -1;
+        tg[i] = has ? S.gs(l, S.cur[l])[j] : -1;
     }
 }
 
@@ -565,7 +566,8 @@ int class_of(int k)
 }
 
 
-size_t red_lds(bool reduce) { return reduce ? sizeof(RedLds) : 0; }
+size_t red_lds(const RedArgs& r) { return r.active ? red_lds_bytes(r.topk, r.bins) : 0; }
+size_t red_lds(const thoi_reduce* r) { return r ? red_lds_bytes(r->topk, r->hist_bins) : 0; }
 
 }  // namespace
 }  // namespace thoi

@@ -178,7 +178,7 @@ __global__ __launch_bounds__(kTile) void k_eval_multi(EvalArgs a, MultiArgs m, i
     double* sIsd = reinterpret_cast<double*>(smem + off);
     double* sLogd = sIsd + nmax;
     uint64_t* sBin = reinterpret_cast<uint64_t*>(sLogd + nmax);
-    RedLds& Rl = *reinterpret_cast<RedLds*>(smem + lane_stage_bytes(nmax, KHI, sizeof(F)));
+    RedLds Rl = red_view(smem + lane_stage_bytes(nmax, KHI, sizeof(F)), red.topk, red.bins);
     const int64_t G = gridDim.x;
     const int64_t u0 = (int64_t)blockIdx.x * U / G, u1 = ((int64_t)blockIdx.x + 1) * U / G;
     if (u0 >= u1) return;                                  // uniform
@@ -469,7 +469,7 @@ size_t multi_ws_bytes(const int32_t* N_d, int64_t D, int32_t kmin, int32_t kmax,
 size_t multi_lds_bytes(int32_t nmax, int32_t kmax, const thoi_eval_opts* opts)
 {
     const int fsize = opts->precision == THOI_FP64 ? 8 : 4;
-    size_t need = lane_stage_bytes(nmax, kF32LaneMax, fsize) + red_lds(opts->reduce != nullptr);
+    size_t need = lane_stage_bytes(nmax, kF32LaneMax, fsize) + red_lds(opts->reduce);
     if (opts->precision == THOI_FP32_REFINE) {
         const size_t r = refine_multi_lds(nmax, kmax);
         need = need > r ? need : r;
@@ -572,7 +572,7 @@ thoi_status launch_multi(const double* Sigma, const int32_t* N_d, const int32_t*
         for (int c = 0; c < sh.ncls; ++c) {
             if (units[c] == 0) continue;
             const int64_t G = class_grid(units[c], opts->grid_blocks);
-            const size_t lds = lane_stage_bytes(nmax, sh.cls[c].hi, opts->precision == THOI_FP64 ? 8 : 4) + red_lds(reduce);
+            const size_t lds = lane_stage_bytes(nmax, sh.cls[c].hi, opts->precision == THOI_FP64 ? 8 : 4) + red_lds(red);
             MultiKernel kern;
             if (opts->precision == THOI_FP64) kern = reduce ? multi_kernel_r<double, true>(c) : multi_kernel_r<double, false>(c);
             else kern = reduce ? multi_kernel_r<float, true>(c) : multi_kernel_r<float, false>(c);

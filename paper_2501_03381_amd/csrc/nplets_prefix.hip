@@ -324,7 +324,7 @@ __global__ __launch_bounds__(kPfxThreads) void k_eval_prefix(EvalArgs a, PfxTabl
     const size_t off = ((size_t)N * N * sizeof(F) + 15) / 16 * 16;
     double* sIsd = reinterpret_cast<double*>(smem + off);
     double* sLogd = sIsd + N;
-    RedLds& Rl = *reinterpret_cast<RedLds*>(smem + pfx_stage_bytes(N, sizeof(F)));
+    RedLds Rl = red_view(smem + pfx_stage_bytes(N, sizeof(F)), red.topk, red.bins);
     if (threadIdx.x == 0) bias_for(a.bias, k, sbias[0], sbias[1], sbias[2]);
     stage_corr<F>(a.Sigma + (int64_t)d * N * N, N, sR, sIsd, sLogd);
     if constexpr (RED) red_begin(Rl, red.topk, red.bins);
@@ -384,15 +384,15 @@ int64_t pfx_blocks(int N, int k, int L)
     return nb;
 }
 
-size_t pfx_lds_bytes(int N, int fsize, bool reduce)
+size_t pfx_lds_bytes(int N, int fsize, size_t red_bytes)
 {
-    return pfx_stage_bytes(N, fsize) + (reduce ? sizeof(RedLds) : 0);
+    return pfx_stage_bytes(N, fsize) + red_bytes;
 }
 
 void pfx_launch(bool f64, int cls, bool reduce, const EvalArgs& a, const PfxTable& t, const RedArgs& red,
                 int64_t nblk, int D, hipStream_t s)
 {
-    const size_t lds = pfx_lds_bytes(a.N, f64 ? 8 : 4, reduce);
+    const size_t lds = pfx_lds_bytes(a.N, f64 ? 8 : 4, red_lds(red));
     static_assert(kPfxF32Classes[0].lo == 3 && kPfxF32Classes[0].hi == 8 && kPfxF32Classes[1].hi == 12 &&
                       kPfxF32Classes[2].hi == 16 && kPfxF64Classes[1].hi == 12,
                   "class table");

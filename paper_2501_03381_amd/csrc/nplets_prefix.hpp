@@ -36,8 +36,8 @@ struct PfxTable {
 int pfx_tails(int N, int k, int64_t D);
 // Blocks (4 units of 64 prefixes x L tails) of order k over N variables.
 int64_t pfx_blocks(int N, int k, int L);
-// LDS bytes of a prefix-engine workgroup.
-size_t pfx_lds_bytes(int N, int fsize, bool reduce);
+// LDS bytes of a prefix-engine workgroup (red_bytes: the reducer's share, 0 without reduction).
+size_t pfx_lds_bytes(int N, int fsize, size_t red_bytes);
 // Launch prefix class `cls` (FP64 when f64) over D datasets.
 void pfx_launch(bool f64, int cls, bool reduce, const EvalArgs& a, const PfxTable& t, const RedArgs& red,
                 int64_t nblk, int D, hipStream_t s);

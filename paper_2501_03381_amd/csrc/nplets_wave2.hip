@@ -182,7 +182,7 @@ __host__ __device__ inline size_t w2_stage_bytes(int N, bool reduce)
 // n-plets (lexicographic successors in RANGE mode, so only the first of a run is unranked).  In
 // reduce mode the chunk's results go to the workgroup's reducer together.
 template <int MODE, bool RED>
-__global__ __launch_bounds__(kPairThreads) void k_eval_pair(EvalArgs a, PieceTable tab, RedArgs red, int klo, int kmax)
+__global__ __launch_bounds__(kPairThreads, 4) void k_eval_pair(EvalArgs a, PieceTable tab, RedArgs red, int klo, int kmax)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double sbias[3];
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kPairThreads) void k_eval_pair(EvalArgs a, PieceTab
     double* res_v = reinterpret_cast<double*>(scidx + kPairHalves * kW2Max);
     int64_t* res_g = reinterpret_cast<int64_t*>(res_v + kPairThreads);
     int* res_ok = reinterpret_cast<int*>(res_g + kPairThreads);
-    RedLds& S = *reinterpret_cast<RedLds*>(smem + w2_stage_bytes(N, RED));
+    RedLds S = red_view(smem + w2_stage_bytes(N, RED), red.topk, red.bins);
     if (threadIdx.x == 0) bias_for(a.bias, k, sbias[0], sbias[1], sbias[2]);
     stage_corr<double>(a.Sigma + (int64_t)d * N * N, N, sR, sIsd, sLogd);
     if constexpr (RED) red_begin(S, red.topk, red.bins);
@@ -577,15 +577,15 @@ void refine_launch(int mode, const EvalArgs& a, const RangeOrders& ro, const Red
     else hipLaunchKernelGGL(k_refine<THOI_SEL_MASK>, dim3(G), dim3(kRefineThreads), lds, s, a, ro, red);
 }
 
-size_t pair_lds_bytes(int N, bool reduce)
+size_t pair_lds_bytes(int N, size_t red_bytes)
 {
-    return w2_stage_bytes(N, reduce) + (reduce ? sizeof(RedLds) : 0);
+    return w2_stage_bytes(N, red_bytes > 0) + red_bytes;
 }
 
 void pair_launch(int mode, bool reduce, const EvalArgs& a, const PieceTable& t, const RedArgs& red, int klo, int kmax,
                  int64_t nblk, hipStream_t s)
 {
-    const size_t lds = pair_lds_bytes(a.N, reduce);
+    const size_t lds = pair_lds_bytes(a.N, red_lds(red));
     const dim3 grid((unsigned)nblk, (unsigned)a.D);
     if (mode == THOI_SEL_RANGE) {
         if (reduce) hipLaunchKernelGGL((k_eval_pair<THOI_SEL_RANGE, true>), grid, dim3(kPairThreads), lds, s, a, t, red, klo, kmax);

@@ -10,8 +10,8 @@ constexpr int kW2Max = 32;   // largest order of the pair engine
 constexpr int kPairThreads = 256;                 // threads per pair-engine workgroup
 constexpr int kPairHalves = kPairThreads / 32;    // n-plets factored at once per workgroup
 
-// LDS bytes of a pair-engine workgroup.
-size_t pair_lds_bytes(int N, bool reduce);
+// LDS bytes of a pair-engine workgroup (red_bytes: the reducer's share, 0 without reduction).
+size_t pair_lds_bytes(int N, size_t red_bytes);
 // Launch the pair engine over nblk workgroups per dataset: a.wave_tile n-plets of one order per
 // workgroup (RANGE pieces of t, LIST / MASK buckets) of orders klo..kmax.
 void pair_launch(int mode, bool reduce, const EvalArgs& a, const PieceTable& t, const RedArgs& red, int klo, int kmax,

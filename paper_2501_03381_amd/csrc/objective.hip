@@ -40,7 +40,8 @@ __global__ __launch_bounds__(kObjTile) void k_objective(const void* __restrict__
                                                         WsHeader* hdr)
 {
     const VT* v = static_cast<const VT*>(vals);
-    __shared__ RedLds S;
+    __shared__ __align__(16) unsigned char sred[red_lds_bytes(kRedMaxK, kRedMaxBins)];
+    RedLds S = red_view(sred, red.topk, red.bins);
     if constexpr (RED) red_begin(S, red.topk, red.bins);
     const int64_t b0 = (int64_t)blockIdx.x * per_blk;
     const int64_t b1 = min(B, b0 + per_blk);

@@ -43,16 +43,44 @@ struct RedArgs {
     double lo[THOI_MAX_K + 1], hi[THOI_MAX_K + 1];
 };
 
+// The reducer's LDS, sized by the call's K and bin count: views into a workgroup's shared memory.
+// Layout from a 16-byte aligned base: key [2 lists][2 buffers][K] u64 | g [2][2][K] i64 |
+// candidates ck, cg [kRedCand] | hist [bins + 2] u32 | cur [2], nc.
+constexpr int kRedCand = 256;        // candidates per offer: at most one per thread of a workgroup
 struct RedLds {
-    uint64_t key[2][2][kRedMaxK];    // [list][buffer][slot]
-    int64_t g[2][2][kRedMaxK];
-    uint64_t ck[kRedMaxK];           // candidate scratch
-    int64_t cg[kRedMaxK];
-    unsigned int hist[kRedMaxBins + 2];
-    int cur[2];
-    int nc;
-    int pad;
+    uint64_t* key;
+    int64_t* g;
+    uint64_t* ck;
+    int64_t* cg;
+    unsigned int* hist;
+    int* cur;
+    int* nc;
+    int K;
+    __device__ __forceinline__ uint64_t* keys(int l, int b) const { return key + (2 * l + b) * K; }
+    __device__ __forceinline__ int64_t* gs(int l, int b) const { return g + (2 * l + b) * K; }
 };
+
+__host__ __device__ constexpr size_t red_lds_bytes(int K, int bins)
+{
+    const size_t lists = (size_t)4 * (K > 0 ? K : 1) * 16;
+    const size_t b = lists + (size_t)kRedCand * 16 + (size_t)(bins + 2) * 4 + 16;
+    return (b + 15) / 16 * 16;
+}
+
+__device__ __forceinline__ RedLds red_view(unsigned char* base, int K, int bins)
+{
+    RedLds S;
+    const int Kc = K > 0 ? K : 1;
+    S.K = Kc;
+    S.key = reinterpret_cast<uint64_t*>(base);
+    S.g = reinterpret_cast<int64_t*>(S.key + 4 * Kc);
+    S.ck = reinterpret_cast<uint64_t*>(S.g + 4 * Kc);
+    S.cg = reinterpret_cast<int64_t*>(S.ck + kRedCand);
+    S.hist = reinterpret_cast<unsigned int*>(S.cg + kRedCand);
+    S.cur = reinterpret_cast<int*>(S.hist + bins + 2);
+    S.nc = S.cur + 2;
+    return S;
+}
 
 // total order on doubles as uint64 (-0.0 folded onto +0.0)
 __device__ __forceinline__ uint64_t red_okey(double x)
@@ -87,9 +115,8 @@ __device__ __forceinline__ double red_list_val(int list, uint64_t key)
 __device__ __forceinline__ void red_begin(RedLds& S, int K, int bins)
 {
     for (int i = threadIdx.x; i < 2 * 2 * K; i += blockDim.x) {
-        const int l = i / (2 * K), r = i % (2 * K), b = r / K, s = r % K;
-        S.key[l][b][s] = kKeyEmpty;
-        S.g[l][b][s] = kGEmpty;
+        S.key[i] = kKeyEmpty;
+        S.g[i] = kGEmpty;
     }
     for (int i = threadIdx.x; i < bins + 2; i += blockDim.x) S.hist[i] = 0;
     if (threadIdx.x == 0) { S.cur[0] = S.cur[1] = 0; }
@@ -100,10 +127,10 @@ __device__ __forceinline__ void red_begin(RedLds& S, int K, int bins)
 __device__ __forceinline__ void red_merge_sorted(RedLds& S, int l, int K, const uint64_t* bk, const int64_t* bg, int nb)
 {
     const int c = S.cur[l];
-    const uint64_t* ak = S.key[l][c];
-    const int64_t* ag = S.g[l][c];
-    uint64_t* ok = S.key[l][c ^ 1];
-    int64_t* og = S.g[l][c ^ 1];
+    const uint64_t* ak = S.keys(l, c);
+    const int64_t* ag = S.gs(l, c);
+    uint64_t* ok = S.keys(l, c ^ 1);
+    int64_t* og = S.gs(l, c ^ 1);
     const int na = K;
     for (int i = threadIdx.x; i < K; i += blockDim.x) {
         // co-rank: a = how many of the first i outputs come from A
@@ -126,17 +153,17 @@ __device__ __forceinline__ void red_merge_sorted(RedLds& S, int l, int K, const 
 __device__ __forceinline__ void red_offer(RedLds& S, int l, int K, bool valid, uint64_t key, int64_t g)
 {
     const int c = S.cur[l];
-    const bool cand = valid && red_less(key, g, S.key[l][c][K - 1], S.g[l][c][K - 1]);
+    const bool cand = valid && red_less(key, g, S.keys(l, c)[K - 1], S.gs(l, c)[K - 1]);
     if (!__syncthreads_or(cand)) return;
-    if (threadIdx.x == 0) S.nc = 0;
+    if (threadIdx.x == 0) *S.nc = 0;
     __syncthreads();
     if (cand) {
-        const int slot = atomicAdd(&S.nc, 1);
+        const int slot = atomicAdd(S.nc, 1);
         S.ck[slot] = key;
         S.cg[slot] = g;
     }
     __syncthreads();
-    const int nc = S.nc;
+    const int nc = *S.nc;
     int P = 1;
     while (P < nc) P <<= 1;
     for (int i = nc + threadIdx.x; i < P; i += blockDim.x) { S.ck[i] = kKeyEmpty; S.cg[i] = kGEmpty; }
@@ -184,7 +211,7 @@ __device__ __forceinline__ void red_end(RedLds& S, const RedArgs& r, WsHeader* h
         __shared__ uint32_t slot;
         if (threadIdx.x == 0) {
             // an all-empty segment is skipped
-            const bool any = S.key[0][S.cur[0]][0] != kKeyEmpty;
+            const bool any = S.keys(0, S.cur[0])[0] != kKeyEmpty;
             slot = any ? atomicAdd(r.seg_next, 1u) : 0xffffffffu;
             if (any && slot >= r.seg_cap) raise_status(hdr, THOI_EWORKSPACE);
         }
@@ -194,8 +221,8 @@ __device__ __forceinline__ void red_end(RedLds& S, const RedArgs& r, WsHeader* h
             if (threadIdx.x == 0) { r.seg_hdr[s].d = d; r.seg_hdr[s].k = k; }
             for (int i = threadIdx.x; i < 2 * K; i += blockDim.x) {
                 const int l = i / K, j = i % K;
-                r.seg_key[((int64_t)s * 2 + l) * K + j] = S.key[l][S.cur[l]][j];
-                r.seg_g[((int64_t)s * 2 + l) * K + j] = S.g[l][S.cur[l]][j];
+                r.seg_key[((int64_t)s * 2 + l) * K + j] = S.keys(l, S.cur[l])[j];
+                r.seg_g[((int64_t)s * 2 + l) * K + j] = S.gs(l, S.cur[l])[j];
             }
         }
     }
