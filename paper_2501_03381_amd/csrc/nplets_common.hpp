@@ -261,10 +261,19 @@ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 // packed lower triangle of an order-K matrix (at least one slot)
 template <int K> constexpr int kTri = K * (K + 1) / 2 > 0 ? K * (K + 1) / 2 : 1;
 
-// Factor the packed lower triangle a of R_S (unit diagonal) in registers.
-template <typename F, int K>
-__device__ __forceinline__ FactorOut<F> lane_factor_tri(F (&a)[kTri<K>])
+// Factor R_S in registers; entry(i, j) (j < i) returns its (i, j) entry, the diagonal is 1.  The
+// gather is part of this function so that the register allocation sees gather and factorisation
+// together.
+template <typename F, int K, typename Entry>
+__device__ __forceinline__ FactorOut<F> lane_factor_by(Entry&& entry)
 {
+    F a[kTri<K>];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+#pragma unroll
+        for (int j = 0; j < i; ++j) a[tri(i, j)] = entry(i, j);
+        a[tri(i, i)] = F(1);
+    }
     LogProd<F> det;
     bool ok = true;
     // right-looking Cholesky, L overwrites the strict lower triangle and the diagonal slot j
@@ -319,16 +328,7 @@ __device__ __forceinline__ FactorOut<F> lane_factor_tri(F (&a)[kTri<K>])
 template <typename F, int K>
 __device__ __forceinline__ FactorOut<F> lane_factor(const int (&c)[K > 0 ? K : 1], const F* __restrict__ sR, int N)
 {
-    F a[kTri<K>];
-    // the strict lower triangle of R_S; the diagonal is 1
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-        const F* row = sR + c[i] * N;
-#pragma unroll
-        for (int j = 0; j < i; ++j) a[tri(i, j)] = row[c[j]];
-        a[tri(i, i)] = F(1);
-    }
-    return lane_factor_tri<F, K>(a);
+    return lane_factor_by<F, K>([&](int i, int j) { return sR[c[i] * N + c[j]]; });
 }
 
 // ------------------------------------------------------------------------------------------------

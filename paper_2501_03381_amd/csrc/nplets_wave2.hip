@@ -394,16 +394,15 @@ __device__ __forceinline__ void refine_lane(const EvalArgs& a, const RangeOrders
         }
     }
     double sumlogd = 0.0;
-    double t[kTri<KP>];
+    FactorOut<double> f;
     if constexpr (STAGED) {
         // the dataset's correlation matrix and log variances are staged in LDS
+        if (a.write_H) {
 #pragma unroll
-        for (int i = 0; i < KP; ++i) {
-            if (a.write_H && i < k) sumlogd += sLogd[c[i]];
-#pragma unroll
-            for (int j = 0; j < i; ++j) t[tri(i, j)] = i < k ? sR[c[i] * N + c[j]] : 0.0;
-            t[tri(i, i)] = 1.0;
+            for (int i = 0; i < KP; ++i)
+                if (i < k) sumlogd += sLogd[c[i]];
         }
+        f = lane_factor_by<double, KP>([&](int i, int j) { return i < k ? sR[c[i] * N + c[j]] : 0.0; });
     } else {
         const double* Sg = a.Sigma + (int64_t)d * N * N;
         double sd[KP];
@@ -416,14 +415,9 @@ __device__ __forceinline__ void refine_lane(const EvalArgs& a, const RangeOrders
                 if (a.write_H) sumlogd += log(di);
             }
         }
-#pragma unroll
-        for (int i = 0; i < KP; ++i) {
-#pragma unroll
-            for (int j = 0; j < i; ++j) t[tri(i, j)] = i < k ? Sg[(int64_t)c[i] * N + c[j]] * sd[i] * sd[j] : 0.0;
-            t[tri(i, i)] = 1.0;
-        }
+        f = lane_factor_by<double, KP>(
+            [&](int i, int j) { return i < k ? Sg[(int64_t)c[i] * N + c[j]] * sd[i] * sd[j] : 0.0; });
     }
-    const FactorOut<double> f = lane_factor_tri<double, KP>(t);
     refine_store(a, ro, red, MODE, o, d, pos, k, f, sumlogd);
 }
 
@@ -568,9 +562,10 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine(EvalArgs a, RangeOrde
 
 void refine_launch(int mode, const EvalArgs& a, const RangeOrders& ro, const RedArgs& red, hipStream_t s)
 {
-    // enough workgroups for every queue slot to be one thread's, up to four rounds of a full GPU
+    // one workgroup per CU at most (the kernel runs one wave per SIMD); larger queues take more
+    // rounds inside the kernel, and an empty queue dispatches a single round of workgroups
     const int64_t need = ((int64_t)a.refine_cap + kRefineThreads - 1) / kRefineThreads;
-    const unsigned G = (unsigned)(need < 1024 ? (need > 0 ? need : 1) : 1024);
+    const unsigned G = (unsigned)(need < 256 ? (need > 0 ? need : 1) : 256);
     const size_t lds = a.N <= kRefineStageMaxN ? ((size_t)a.N * a.N + 2 * (size_t)a.N) * sizeof(double) : 0;
     if (mode == THOI_SEL_RANGE) hipLaunchKernelGGL(k_refine<THOI_SEL_RANGE>, dim3(G), dim3(kRefineThreads), lds, s, a, ro, red);
     else if (mode == THOI_SEL_LIST) hipLaunchKernelGGL(k_refine<THOI_SEL_LIST>, dim3(G), dim3(kRefineThreads), lds, s, a, ro, red);
