@@ -131,6 +131,11 @@ typedef struct {
     int32_t grid_blocks;         /* tuning: workgroups of a persistent launch; 0 = library choice  */
     int32_t engine;              /* THOI_ENGINE_*: how whole orders of a RANGE selection are       */
                                  /* factored (same results to rounding; other selections ignore it) */
+    /* tuning per register class of a RANGE selection (index: the precision's class table, FP32  */
+    /* orders {0-8, 9-12, 13-16, 17-20, 21-24}, FP64 {0-6, 7-10, 11-14, 15-18}); 0 = seg_tiles /  */
+    /* library choice.  Work split only: results are the same for every value.                   */
+    int32_t class_seg_tiles[8];  /* tiles of 256 lanes per workgroup                               */
+    int32_t class_lanes[8];      /* n-plets per lane: 1, or 2 where the class has register room   */
 } thoi_eval_opts;
 
 /*

@@ -121,13 +121,24 @@ _ENGINE = {"auto": B.THOI_ENGINE_AUTO, "factor": B.THOI_ENGINE_FACTOR, "prefix":
 
 def make_opts(precision: str = "fp32_refine", out_dtype: torch.dtype = torch.float32, vif_tau: float = 1e3,
               bias_correct: bool = False, T: int = 0, write_entropy: bool = False, seg_tiles: int = 0,
-              grid_blocks: int = 0, engine: str = "auto") -> B.ThoiEvalOpts:
+              grid_blocks: int = 0, engine: str = "auto", class_seg_tiles=None, class_lanes=None) -> B.ThoiEvalOpts:
     """Evaluation options; engine: "auto", "factor" (one factorisation per n-plet) or "prefix"
-    (prefix sharing for the whole orders of a RANGE selection)."""
-    return B.ThoiEvalOpts(precision=_PREC[precision], out_dtype=_DT[out_dtype], vif_tau=float(vif_tau),
-                          bias_correct=int(bool(bias_correct)), T=int(T), write_entropy=int(bool(write_entropy)),
-                          reduce=None, seg_tiles=int(seg_tiles), grid_blocks=int(grid_blocks),
-                          engine=_ENGINE[engine])
+    (prefix sharing for the whole orders of a RANGE selection).  class_seg_tiles / class_lanes:
+    per register class of a RANGE selection, tiles per workgroup and n-plets per lane (0 = the
+    library's choice; see tune.py)."""
+    o = B.ThoiEvalOpts(precision=_PREC[precision], out_dtype=_DT[out_dtype], vif_tau=float(vif_tau),
+                       bias_correct=int(bool(bias_correct)), T=int(T), write_entropy=int(bool(write_entropy)),
+                       reduce=None, seg_tiles=int(seg_tiles), grid_blocks=int(grid_blocks),
+                       engine=_ENGINE[engine])
+    for c, v in enumerate(class_seg_tiles or ()):
+        o.class_seg_tiles[c] = int(v)
+    for c, v in enumerate(class_lanes or ()):
+        o.class_lanes[c] = int(v)
+    return o
+
+
+def _untuned(opts: B.ThoiEvalOpts) -> bool:
+    return opts.seg_tiles == 0 and not any(opts.class_seg_tiles) and not any(opts.class_lanes)
 
 
 # ------------------------------------------------------------------------------------------------ evaluation
@@ -138,7 +149,15 @@ class Evaluator:
     """
 
     def __init__(self, D: int, N: int, sel: B.ThoiNplets, opts: B.ThoiEvalOpts, device, out_dtype=torch.float32,
-                 keep=()):
+                 keep=(), tuned: bool = True):
+        if tuned and sel.mode == B.THOI_SEL_RANGE and _untuned(opts):
+            # per-class launch knobs from the autotuner's cache, when it holds this shape
+            from . import tune
+            knobs = tune.lookup_range(device, opts.precision, N, D)
+            if knobs is not None:
+                opts = B.ThoiEvalOpts.from_buffer_copy(opts)
+                for c in range(8):
+                    opts.class_seg_tiles[c], opts.class_lanes[c] = knobs[0][c], knobs[1][c]
         self.D, self.N, self.sel, self.opts = D, N, sel, opts
         self.keep = keep  # tensors the selection points to
         self.nout = _n_out(sel)
@@ -229,6 +248,12 @@ class MultiEvaluator:
         self.D, self.kmin, self.kmax = len(self.N_d), kmin, kmax
         self.offsets = B.thoi_multi_offsets(self.N_d, kmin, kmax)
         self.total = int(self.offsets[-1])
+        if seg_tiles == 0 and grid_blocks == 0 and len(self.N_d) > 0:
+            # launch knobs from the autotuner's cache, when it holds this shape
+            from . import tune
+            knobs = tune.lookup_multi(device, _PREC[precision], self.N_d, kmin, kmax)
+            if knobs is not None:
+                seg_tiles, grid_blocks = knobs
         self.opts = make_opts(precision, out_dtype, 1e3, bias_correct, 0, write_entropy, seg_tiles, grid_blocks)
         self.reduce_state = reduce_state
         if reduce_state is not None:

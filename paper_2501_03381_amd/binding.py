@@ -77,6 +77,8 @@ class ThoiEvalOpts(ctypes.Structure):
         ("seg_tiles", ctypes.c_int32),
         ("grid_blocks", ctypes.c_int32),
         ("engine", ctypes.c_int32),
+        ("class_seg_tiles", ctypes.c_int32 * 8),
+        ("class_lanes", ctypes.c_int32 * 8),
     ]
 
 

@@ -165,6 +165,10 @@ thoi_status thoi::check_eval(const double* Sigma, int64_t D, int32_t N, const th
     if (opts->seg_tiles < 0 || opts->grid_blocks < 0) return THOI_EINVAL;
     if (opts->engine < THOI_ENGINE_AUTO || opts->engine > THOI_ENGINE_PREFIX) return THOI_EINVAL;
     if (opts->seg_tiles > 4096) return THOI_EUNSUPPORTED;
+    for (int c = 0; c < 8; ++c) {
+        if (opts->class_seg_tiles[c] < 0 || opts->class_lanes[c] < 0 || opts->class_lanes[c] > 2) return THOI_EINVAL;
+        if (opts->class_seg_tiles[c] > 4096) return THOI_EUNSUPPORTED;
+    }
     if (forward) {
         if (opts->reduce) {
             const thoi_reduce* r = opts->reduce;

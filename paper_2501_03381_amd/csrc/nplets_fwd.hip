@@ -21,7 +21,7 @@ namespace thoi {
 
 namespace {
 
-template <typename F, int KLO, int KHI, int MODE, bool RED>
+template <typename F, int KLO, int KHI, int MODE, bool RED, int S = lane_per_thread<F>(KHI, MODE)>
 __global__ __launch_bounds__(kTile) void k_eval_lane(EvalArgs a, PieceTable tab, RedArgs red)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -29,7 +29,6 @@ __global__ __launch_bounds__(kTile) void k_eval_lane(EvalArgs a, PieceTable tab,
     const int N = a.N;
     const int d = blockIdx.y;
     const int64_t blk = blockIdx.x;
-    constexpr int S = lane_per_thread<F>(KHI, MODE);
     const int64_t per_blk = (int64_t)kTile * S * a.seg_tiles;
     // which order / piece does this workgroup belong to (uniform in the workgroup)
     int k = -1;
@@ -199,6 +198,8 @@ struct Plan {
     int64_t wblk_hi;     // wave-engine workgroups (orders above kW2Max)
     int wkmax;
     int seg_tiles, wave_tile, wave_tile_hi;
+    int cls_seg[8];      // per class: tiles per workgroup (RANGE: tunable per class; else seg_tiles)
+    int cls_S[8];        // per class: n-plets per lane
     int64_t seg_cap;
     bool serial;     // every launch on the caller's stream (no side streams)
     int npcls;       // prefix engine: classes, their order tables and workgroups
@@ -235,8 +236,9 @@ bool use_prefix(int engine, bool reduce, bool f64, int N, int k, int64_t D)
 }
 
 template <typename F>
-Plan make_plan(int N, int64_t D, const thoi_nplets* sel, bool reduce, int precision, int seg_tiles_hint, int engine)
+Plan make_plan(int N, int64_t D, const thoi_nplets* sel, bool reduce, const thoi_eval_opts* o)
 {
+    const int precision = o->precision, seg_tiles_hint = o->seg_tiles, engine = o->engine;
     Plan P{};
     const bool f64 = sizeof(F) == 8;
     P.npcls = f64 ? (int)(sizeof(kPfxF64Classes) / sizeof(PfxClass)) : (int)(sizeof(kPfxF32Classes) / sizeof(PfxClass));
@@ -280,13 +282,23 @@ Plan make_plan(int N, int64_t D, const thoi_nplets* sel, bool reduce, int precis
         if (sel_kmax(sel, N) > lane_max) pair_cnt = Bn;
         if (sel_kmax(sel, N) > kW2Max) wave_cnt = Bn;
     }
+    const bool range = sel->mode == THOI_SEL_RANGE;
     for (int c = 0; c < P.ncls; ++c) {
-        // threads of class c at seg_tiles: about cls_cnt / (S * seg_tiles) plus one tile per piece
-        const int S = sel->mode == THOI_SEL_RANGE ? lane_per_thread<F>(cls[c].hi, THOI_SEL_RANGE) : 1;
-        const int64_t threads = cls_cnt[c] / S + (int64_t)kTile * (kMaxPieces + 1);
+        P.cls_S[c] = range ? lane_per_thread<F>(cls[c].hi, THOI_SEL_RANGE) : 1;
+        if (range && o->class_lanes[c] == 1) P.cls_S[c] = 1;
+        // threads of class c: about cls_cnt / S plus one tile per piece; the grid stays below
+        // kMaxGridItems by walking more tiles per workgroup
+        const int64_t threads = cls_cnt[c] / P.cls_S[c] + (int64_t)kTile * (kMaxPieces + 1);
         const int64_t need = (threads + kMaxGridItems - 1) / kMaxGridItems;
-        if (need > P.seg_tiles) P.seg_tiles = (int)need;
+        if (range) {
+            P.cls_seg[c] = o->class_seg_tiles[c] > 0 ? o->class_seg_tiles[c] : P.seg_tiles;
+            if (need > P.cls_seg[c]) P.cls_seg[c] = (int)need;
+        } else if (need > P.seg_tiles) {
+            P.seg_tiles = (int)need;
+        }
     }
+    if (!range)
+        for (int c = 0; c < P.ncls; ++c) P.cls_seg[c] = P.seg_tiles;
     // pair engine: about 16384 workgroups in output mode and 8192 in reduce mode over all D
     // datasets (each reducing workgroup leaves one segment of top-K lists to merge), at least one
     // chunk of kPairThreads n-plets per reducing workgroup; a multiple of kPairHalves n-plets per
@@ -338,7 +350,7 @@ Plan make_plan(int N, int64_t D, const thoi_nplets* sel, bool reduce, int precis
                 p.cnt = hi - lo;
                 if (k <= lane_max) {
                     const int c = class_of<F>(k);
-                    const int64_t pb = per_blk * lane_per_thread<F>(cls[c].hi, THOI_SEL_RANGE);
+                    const int64_t pb = (int64_t)kTile * P.cls_seg[c] * P.cls_S[c];
                     p.blk0 = P.nblk[c];
                     P.nblk[c] += (p.cnt + pb - 1) / pb;
                     P.tabs[c].p[P.tabs[c].n++] = p;
@@ -400,8 +412,8 @@ EvalWs eval_layout(int64_t D, int32_t N, const thoi_nplets* sel, const thoi_eval
     }
     if (reduce && opts->reduce->topk > 0) {
         const int K = opts->reduce->topk;
-        const Plan P = opts->precision == THOI_FP64 ? make_plan<double>(N, D, sel, true, opts->precision, opts->seg_tiles, opts->engine)
-                                                    : make_plan<float>(N, D, sel, true, opts->precision, opts->seg_tiles, opts->engine);
+        const Plan P = opts->precision == THOI_FP64 ? make_plan<double>(N, D, sel, true, opts)
+                                                    : make_plan<float>(N, D, sel, true, opts);
         const int64_t segs = P.seg_cap * D;
         w.seg_cap = (uint32_t)(segs > 0 ? segs : 1);
         w.seg_key_off = off; off = align_up(off + (size_t)w.seg_cap * 2 * K * 8, 256);
@@ -416,31 +428,43 @@ EvalWs eval_layout(int64_t D, int32_t N, const thoi_nplets* sel, const thoi_eval
 
 typedef void (*LaneKernel)(EvalArgs, PieceTable, RedArgs);
 
+// Class kernel with S n-plets per lane: S = 1 is instantiated as a tuning alternative where the
+// default is 2 (RANGE mode, classes with register room).
+template <typename F, int KLO, int KHI, int MODE, bool RED>
+LaneKernel lane_kernel_s(int S)
+{
+    constexpr int Sd = lane_per_thread<F>(KHI, MODE);
+    if constexpr (Sd > 1) {
+        if (S == 1) return k_eval_lane<F, KLO, KHI, MODE, RED, 1>;
+    }
+    return k_eval_lane<F, KLO, KHI, MODE, RED, Sd>;
+}
+
 template <typename F, int MODE, bool RED>
-LaneKernel lane_kernel_r(int cls)
+LaneKernel lane_kernel_r(int cls, int S)
 {
     if constexpr (sizeof(F) == 4) {
         switch (cls) {
-            case 0: return k_eval_lane<F, 0, 8, MODE, RED>;
-            case 1: return k_eval_lane<F, 9, 12, MODE, RED>;
-            case 2: return k_eval_lane<F, 13, 16, MODE, RED>;
-            case 3: return k_eval_lane<F, 17, 20, MODE, RED>;
-            default: return k_eval_lane<F, 21, 24, MODE, RED>;
+            case 0: return lane_kernel_s<F, 0, 8, MODE, RED>(S);
+            case 1: return lane_kernel_s<F, 9, 12, MODE, RED>(S);
+            case 2: return lane_kernel_s<F, 13, 16, MODE, RED>(S);
+            case 3: return lane_kernel_s<F, 17, 20, MODE, RED>(S);
+            default: return lane_kernel_s<F, 21, 24, MODE, RED>(S);
         }
     } else {
         switch (cls) {
-            case 0: return k_eval_lane<F, 0, 6, MODE, RED>;
-            case 1: return k_eval_lane<F, 7, 10, MODE, RED>;
-            case 2: return k_eval_lane<F, 11, 14, MODE, RED>;
-            default: return k_eval_lane<F, 15, 18, MODE, RED>;
+            case 0: return lane_kernel_s<F, 0, 6, MODE, RED>(S);
+            case 1: return lane_kernel_s<F, 7, 10, MODE, RED>(S);
+            case 2: return lane_kernel_s<F, 11, 14, MODE, RED>(S);
+            default: return lane_kernel_s<F, 15, 18, MODE, RED>(S);
         }
     }
 }
 
 template <typename F, int MODE>
-LaneKernel lane_kernel(int cls, bool reduce)
+LaneKernel lane_kernel(int cls, bool reduce, int S)
 {
-    return reduce ? lane_kernel_r<F, MODE, true>(cls) : lane_kernel_r<F, MODE, false>(cls);
+    return reduce ? lane_kernel_r<F, MODE, true>(cls, S) : lane_kernel_r<F, MODE, false>(cls, S);
 }
 
 typedef void (*WaveKernel)(EvalArgs, PieceTable, RedArgs, int, int);
@@ -477,8 +501,10 @@ void launch_engines(EvalArgs& a, const Plan& P, const RedArgs& red, hipStream_t 
         if (P.nblk[c] == 0) continue;
         const int kb = MODE == THOI_SEL_RANGE ? cls[c].hi : 0;
         const size_t lds = lane_stage_bytes(N, kb, sizeof(F)) + red_lds(red);
-        const LaneKernel kern = lane_kernel<F, MODE>(c, reduce);
-        hipLaunchKernelGGL(kern, dim3((unsigned)P.nblk[c], (unsigned)a.D), dim3(kTile), lds, fan.stream(b++), a,
+        const LaneKernel kern = lane_kernel<F, MODE>(c, reduce, P.cls_S[c]);
+        EvalArgs ac = a;
+        ac.seg_tiles = P.cls_seg[c];
+        hipLaunchKernelGGL(kern, dim3((unsigned)P.nblk[c], (unsigned)a.D), dim3(kTile), lds, fan.stream(b++), ac,
                            P.tabs[c], red);
     }
     // orders above the lane engine: up to kW2Max two n-plets per wavefront (rows in registers),
@@ -619,14 +645,14 @@ thoi_status launch_eval(const double* Sigma, int64_t D, int32_t N, const thoi_np
     if (D == 0 || a.B == 0) return hip_status(hipGetLastError());
 
     if (opts->precision == THOI_FP64) {
-        Plan P = make_plan<double>(N, D, sel, reduce, opts->precision, opts->seg_tiles, opts->engine);
+        Plan P = make_plan<double>(N, D, sel, reduce, opts);
         P.serial = serial;
         a.seg_tiles = P.seg_tiles;
         a.wave_tile = P.wave_tile;
         a.wave_tile_hi = P.wave_tile_hi;
         launch_forward<double>(a, sel, P, red, w, base, s);
     } else {
-        Plan P = make_plan<float>(N, D, sel, reduce, opts->precision, opts->seg_tiles, opts->engine);
+        Plan P = make_plan<float>(N, D, sel, reduce, opts);
         P.serial = serial;
         a.seg_tiles = P.seg_tiles;
         a.wave_tile = P.wave_tile;
@@ -658,8 +684,8 @@ void eval_launch_shape(int32_t N, const thoi_nplets* sel, const thoi_eval_opts* 
                        int64_t* max_items_x)
 {
     const bool reduce = opts->reduce != nullptr;
-    const Plan P = opts->precision == THOI_FP64 ? make_plan<double>(N, 1, sel, reduce, opts->precision, opts->seg_tiles, opts->engine)
-                                                : make_plan<float>(N, 1, sel, reduce, opts->precision, opts->seg_tiles, opts->engine);
+    const Plan P = opts->precision == THOI_FP64 ? make_plan<double>(N, 1, sel, reduce, opts)
+                                                : make_plan<float>(N, 1, sel, reduce, opts);
     int n = 0;
     int64_t mx = 0;
     for (int c = 0; c < P.ncls; ++c) {

@@ -164,7 +164,7 @@ def test_struct_layouts_match_header(B, tmp_path):
         "thoi_nplets": ["mode", "kmin", "kmax", "g_begin", "g_count", "idx", "kmax_list", "mask", "B"],
         "thoi_reduce": ["topk", "hist_bins", "hist_lo_hi", "top_val", "top_g", "hist"],
         "thoi_eval_opts": ["precision", "out_dtype", "vif_tau", "bias_correct", "T", "write_entropy", "reduce",
-                           "seg_tiles", "grid_blocks"],
+                           "seg_tiles", "grid_blocks", "engine", "class_seg_tiles", "class_lanes"],
     }
     src = ["#include <stdio.h>", "#include <stddef.h>", '#include "thoi.h"', "int main(void) {"]
     for st, fs in fields.items():
@@ -252,3 +252,28 @@ def test_launch_plan_stays_below_dispatch_limit(B):
                                           ctypes.byref(B.ThoiEvalOpts(precision=0, out_dtype=0)),
                                           ctypes.byref(ctypes.c_int32()), ctypes.byref(ctypes.c_int64())) \
         == B.THOI_EINVAL
+
+
+def test_tuner_keys_and_cache_lookup(tmp_path, monkeypatch):
+    """The tuner's cache is keyed by (architecture, path, precision, register class, N bucket,
+    dataset-count bucket); lookups assemble the per-class knobs of a shape (no GPU)."""
+    import json
+    from paper_2501_03381_amd import tune
+    monkeypatch.setenv("THOI_TUNE_CACHE", str(tmp_path / "t.json"))
+    assert tune.lookup_range("gfx950", "fp32_refine", 20, 1) is None
+    assert [tune.n_bucket(n) for n in (5, 12, 13, 20, 30, 40, 62)] == \
+        ["N<=12", "N<=12", "N<=16", "N<=24", "N<=32", "N<=48", "N<=62"]
+    assert [tune.d_bucket(d) for d in (1, 2, 64, 65)] == ["D<=1", "D<=8", "D<=64", "D>64"]
+    k1 = tune.range_key("gfx950", "fp32_refine", 1, 20, 1)
+    assert k1 == "gfx950|range|fp32_refine|k9-12|N<=24|D<=1"
+    assert tune.range_key("gfx950", "fp64", 1, 20, 1) == "gfx950|range|fp64|k7-10|N<=24|D<=1"
+    json.dump({k1: {"seg_tiles": 3, "lanes": 1},
+               tune.range_key("gfx950", "fp32_refine", 3, 20, 1): {"seg_tiles": 2, "lanes": 0},
+               tune.multi_key("gfx950", "fp32", [10, 40, 22], 3, 5): {"seg_tiles": 4, "grid_blocks": 512}},
+              open(tmp_path / "t.json", "w"))
+    seg, lanes = tune.lookup_range("gfx950", "fp32_refine", 21, 1)     # same N bucket
+    assert seg == [0, 3, 0, 2, 0, 0, 0, 0] and lanes == [0, 1, 0, 0, 0, 0, 0, 0]
+    assert tune.lookup_range("gfx950", "fp32_refine", 30, 1) is None     # another N bucket
+    assert tune.lookup_range("gfx942", "fp32_refine", 20, 1) is None     # another architecture
+    assert tune.lookup_multi("gfx950", "fp32", [12, 33, 40], 3, 5) == (4, 512)
+    assert tune.lookup_multi("gfx950", "fp32", [12, 33, 40], 3, 6) is None

@@ -119,9 +119,21 @@ def test_tuning_knobs_do_not_change_results(env, tmp_path, monkeypatch):
             outs.append((o.clone(), f.clone()))
         for o, f in outs[1:]:
             assert torch.equal(o, outs[0][0]) and torch.equal(f, outs[0][1])
-    say("tune_range")
-    r = tune.tune_range(Sd, 3, 20, candidates=(1, 2))
-    assert r["seg_tiles"] in (1, 2) and r["ms"] > 0
+        say(f"per-class tiles per workgroup and n-plets per lane give identical RANGE results, {prec}")
+        for cs, cl in (([3, 1, 2, 5, 1, 0, 0, 0], [1, 1, 1, 0, 0, 0, 0, 0]), ([1, 4, 1, 1, 2, 0, 0, 0], [1, 0, 1, 0, 0, 0, 0, 0])):
+            ev = api.Evaluator(1, 20, sel, api.make_opts(prec, odt, class_seg_tiles=cs, class_lanes=cl), Sd.device, odt)
+            o, f = ev(Sd)
+            assert torch.equal(o, outs[0][0]) and torch.equal(f, outs[0][1]), (cs, cl)
+    say("tune_range, then an Evaluator built without knobs takes them from the cache")
+    r = tune.tune_range(Sd, 3, 20, seg_candidates=(1, 2))
+    assert all(v in (0, 1, 2) for v in r["class_seg_tiles"]) and all(v in (0, 1) for v in r["class_lanes"])
+    assert len(r["classes"]) == 4 and all(e["ms"] > 0 for e in r["classes"].values())
+    ev = api.Evaluator(1, 20, sel, api.make_opts("fp32_refine", torch.float32), Sd.device, torch.float32)
+    assert list(ev.opts.class_seg_tiles) == r["class_seg_tiles"] and list(ev.opts.class_lanes) == r["class_lanes"]
+    o, f = ev(Sd)
+    ref = api.Evaluator(1, 20, sel, api.make_opts("fp32_refine", torch.float32), Sd.device, torch.float32,
+                        tuned=False)(Sd)
+    assert torch.equal(o, ref[0]) and torch.equal(f, ref[1])
     Xs = uneven(synth, 20, 8, 20, 500, 1000, 16)
     Sig = [dev(torch, orc.gc_covariance(X)) for X in Xs]
     flat, Ns = api.pack_covariances(Sig)
@@ -132,6 +144,10 @@ def test_tuning_knobs_do_not_change_results(env, tmp_path, monkeypatch):
         o, f = ev(flat)
         res.append(o.clone())
     assert all(torch.equal(res[0], r_) for r_ in res[1:])
-    say("tune_multi")
+    say("tune_multi, then a MultiEvaluator built without knobs takes them from the cache")
     t = tune.tune_multi(flat, Ns, 3, 6, seg_candidates=(1, 4), grid_candidates=(0, 256))
     assert t["seg_tiles"] in (1, 4) and t["grid_blocks"] in (0, 256)
+    ev = api.MultiEvaluator(Ns, 3, 6, flat.device, "fp32_refine")
+    assert (ev.opts.seg_tiles, ev.opts.grid_blocks) == (t["seg_tiles"], t["grid_blocks"])
+    o, f = ev(flat)
+    assert torch.equal(o, res[0])
