@@ -60,7 +60,7 @@ __global__ __launch_bounds__(kTile) void k_eval_lane(EvalArgs a, PieceTable tab,
     if (threadIdx.x == 0) bias_for(a.bias, k, sbias[0], sbias[1], sbias[2]);
     stage_corr<F>(a.Sigma + (int64_t)d * N * N, N, sR, sIsd, sLogd, MODE == THOI_SEL_RANGE ? sBin : nullptr, kb);
     constexpr bool reduce = RED;
-    if constexpr (RED) red_begin(Rl, red.topk, red.bins);
+    if constexpr (RED) red_begin(Rl, red, d, k);
 
     LaneCtx cx;
     cx.d = d;
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(64) void k_eval_wave(EvalArgs a, PieceTable tab, Re
     if constexpr (MODE == THOI_SEL_RANGE) stage_binomials(N, 64, sBin);
     stage_corr<double>(a.Sigma + (int64_t)d * N * N, N, sR, sIsd, sLogd);
     constexpr bool reduce = RED;
-    if constexpr (RED) red_begin(S, red.topk, red.bins);
+    if constexpr (RED) red_begin(S, red, d, k);
 
     const int lane = threadIdx.x;
     const int64_t l0 = (blk - blk0) * wt;
@@ -385,7 +385,7 @@ Plan make_plan(int N, int64_t D, const thoi_nplets* sel, bool reduce, const thoi
 
 struct EvalWs {
     size_t refine_off, korder_off, cnt_off, base_off, blk0_off, cursor_off, perm_off;
-    size_t seg_key_off, seg_g_off, seg_hdr_off, late_off, total;
+    size_t seg_key_off, seg_g_off, seg_hdr_off, late_off, bound_off, clear_end, total;
     uint32_t refine_cap, seg_cap, late_cap;
 };
 
@@ -395,6 +395,12 @@ EvalWs eval_layout(int64_t D, int32_t N, const thoi_nplets* sel, const thoi_eval
     const int64_t B = sel_B(sel);
     const bool reduce = opts->reduce != nullptr;
     size_t off = kWsHeader;
+    if (reduce && opts->reduce->topk > 0) {
+        // admission bounds [D][kmax+1][2], cleared with the header
+        w.bound_off = off;
+        off = align_up(off + (size_t)D * (sel_kmax(sel, N) + 1) * 2 * 8, 256);
+    }
+    w.clear_end = off;
     if (opts->precision == THOI_FP32_REFINE) {
         const int64_t want = D * B;
         const int64_t cap = want < (int64_t(1) << 24) ? want : (int64_t(1) << 24);
@@ -635,13 +641,14 @@ thoi_status launch_eval(const double* Sigma, int64_t D, int32_t N, const thoi_np
         red.late = w.late_cap ? reinterpret_cast<LateEntry*>(base + w.late_off) : nullptr;
         red.late_next = &a.hdr->late_next;
         red.late_cap = w.late_cap;
+        red.bound = r->topk > 0 ? reinterpret_cast<unsigned long long*>(base + w.bound_off) : nullptr;
         for (int k = 0; k <= kmax; ++k) {
             red.lo[k] = r->hist_bins ? r->hist_lo_hi[2 * k] : 0.0;
             red.hi[k] = r->hist_bins ? r->hist_lo_hi[2 * k + 1] : 1.0;
         }
     }
 
-    hipLaunchKernelGGL(k_ws_clear, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t*>(base), (int64_t)(kWsHeader / 4));
+    ws_clear(base, w.clear_end, s);
     if (D == 0 || a.B == 0) return hip_status(hipGetLastError());
 
     if (opts->precision == THOI_FP64) {

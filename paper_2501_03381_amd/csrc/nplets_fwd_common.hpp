@@ -301,8 +301,7 @@ __host__ __device__ inline size_t wave_stage_bytes(int N, int kmax, bool with_bi
 // ------------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_red_final(RedArgs red, WsHeader* hdr)
 {
-    __shared__ __align__(16) unsigned char sred[red_lds_bytes(kRedMaxK, 0)];
-    RedLds S = red_view(sred, red.topk, 0);
+    __shared__ RedFinal S;
     const int k = blockIdx.x, d = blockIdx.y;
     const int K = red.topk;
     if (K <= 0) return;
@@ -311,8 +310,8 @@ __global__ __launch_bounds__(256) void k_red_final(RedArgs red, WsHeader* hdr)
     for (int i = threadIdx.x; i < 2 * K; i += blockDim.x) {
         const int l = i / K, j = i % K;
         const bool has = tg[i] >= 0;
-        S.keys(l, 0)[j] = has ? red_list_key(l, tv[i]) : kKeyEmpty;
-        S.gs(l, 0)[j] = has ? tg[i] : kGEmpty;
+        S.key[l][0][j] = has ? red_list_key(l, tv[i]) : kKeyEmpty;
+        S.g[l][0][j] = has ? tg[i] : kGEmpty;
     }
     if (threadIdx.x == 0) { S.cur[0] = S.cur[1] = 0; }
     __syncthreads();
@@ -333,7 +332,7 @@ __global__ __launch_bounds__(256) void k_red_final(RedArgs red, WsHeader* hdr)
                 for (int l = 0; l < 2; ++l) {
                     const int64_t e = ((int64_t)s * 2 + l) * K;
                     const int c = S.cur[l];
-                    if (red_less(red.seg_key[e], red.seg_g[e], S.keys(l, c)[K - 1], S.gs(l, c)[K - 1]))
+                    if (red_less(red.seg_key[e], red.seg_g[e], S.key[l][c][K - 1], S.g[l][c][K - 1]))
                         cand[l][atomicAdd(&ncand[l], 1)] = s;
                 }
             }
@@ -346,8 +345,8 @@ __global__ __launch_bounds__(256) void k_red_final(RedArgs red, WsHeader* hdr)
                 const uint64_t* bk = red.seg_key + e;
                 const int64_t* bg = red.seg_g + e;
                 const int c = S.cur[l];
-                if (!red_less(bk[0], bg[0], S.keys(l, c)[K - 1], S.gs(l, c)[K - 1])) continue;   // uniform
-                red_merge_sorted(S, l, K, bk, bg, K);
+                if (!red_less(bk[0], bg[0], S.key[l][c][K - 1], S.g[l][c][K - 1])) continue;   // uniform
+                red_final_merge(S, l, K, bk, bg, K);
             }
         }
         __syncthreads();                         // every thread has read ncand before the reset
@@ -364,16 +363,16 @@ __global__ __launch_bounds__(256) void k_red_final(RedArgs red, WsHeader* hdr)
             v = e.v;
             g = e.g;
         }
-        red_offer(S, 0, K, mine, red_list_key(0, v), g);
-        red_offer(S, 1, K, mine, red_list_key(1, v), g);
+        red_final_offer(S, 0, K, mine, red_list_key(0, v), g);
+        red_final_offer(S, 1, K, mine, red_list_key(1, v), g);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < 2 * K; i += blockDim.x) {
         const int l = i / K, j = i % K;
-        const uint64_t key = S.keys(l, S.cur[l])[j];
+        const uint64_t key = S.key[l][S.cur[l]][j];
         const bool has = key != kKeyEmpty;
         tv[i] = has ? red_list_val(l, key) : __builtin_nan("");
-        tg[i] = has ? S.gs(l, S.cur[l])[j] : -1;
+        tg[i] = has ? S.g[l][S.cur[l]][j] : -1;
     }
 }
 
@@ -393,6 +392,15 @@ __global__ void k_red_init(double* top_val, int64_t* top_g, int64_t ntop, unsign
 __global__ void k_ws_clear(uint32_t* p, int64_t n)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// Zero the first `bytes` of a workspace: the header and the admission bounds that follow it.
+inline void ws_clear(void* base, size_t bytes, hipStream_t s)
+{
+    const int64_t n = (int64_t)(bytes / 4);
+    int64_t g = (n + 1023) / 1024;
+    g = g < 1 ? 1 : (g > 1024 ? 1024 : g);
+    hipLaunchKernelGGL(k_ws_clear, dim3((unsigned)g), dim3(256), 0, s, reinterpret_cast<uint32_t*>(base), n);
 }
 
 

@@ -222,7 +222,7 @@ __global__ __launch_bounds__(kTile) void k_eval_multi(EvalArgs a, MultiArgs m, i
                 bp.psi2 = m.t.psi2[d];
                 bias_for(bp, k, sbias[0], sbias[1], sbias[2]);
             }
-            if constexpr (RED) red_begin(Rl, red.topk, red.bins);   // contains a barrier
+            if constexpr (RED) red_begin(Rl, red, (int)d, k);   // contains a barrier
             else __syncthreads();
             staged = (int)d;
             kred = k;
@@ -390,7 +390,7 @@ int class_of_order(const MultiShape& sh, int k)
 
 struct MultiWs {
     size_t N_off, T_off, sig_off, out_off, psi1_off, psi2_off, unit_off;
-    size_t refine_off, seg_key_off, seg_g_off, seg_hdr_off, late_off, total;
+    size_t refine_off, seg_key_off, seg_g_off, seg_hdr_off, late_off, bound_off, clear_end, total;
     uint32_t refine_cap, seg_cap, late_cap;
 };
 
@@ -423,6 +423,12 @@ MultiWs multi_layout(const int32_t* N_d, int64_t D, int kmin, int kmax, const th
     int64_t units[kMaxClasses], entries[kMaxClasses], total = 0;
     multi_counts(N_d, D, kmin, kmax, sh, units, entries, &total);
     size_t off = kWsHeader;
+    if (o->reduce && o->reduce->topk > 0) {
+        // admission bounds [D][kmax+1][2], cleared with the header
+        w.bound_off = off;
+        off = align_up(off + (size_t)D * (kmax + 1) * 2 * 8, 256);
+    }
+    w.clear_end = off;
     w.N_off = off; off = align_up(off + (size_t)D * 4, 256);
     w.T_off = off; off = align_up(off + (size_t)D * 4, 256);
     w.sig_off = off; off = align_up(off + (size_t)D * 8, 256);
@@ -546,13 +552,14 @@ thoi_status launch_multi(const double* Sigma, const int32_t* N_d, const int32_t*
         red.late = w.late_cap ? reinterpret_cast<LateEntry*>(base + w.late_off) : nullptr;
         red.late_next = &a.hdr->late_next;
         red.late_cap = w.late_cap;
+        red.bound = r->topk > 0 ? reinterpret_cast<unsigned long long*>(base + w.bound_off) : nullptr;
         for (int k = 0; k <= kmax; ++k) {
             red.lo[k] = r->hist_bins ? r->hist_lo_hi[2 * k] : 0.0;
             red.hi[k] = r->hist_bins ? r->hist_lo_hi[2 * k + 1] : 1.0;
         }
     }
 
-    hipLaunchKernelGGL(k_ws_clear, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t*>(base), (int64_t)(kWsHeader / 4));
+    ws_clear(base, w.clear_end, s);
     for (int64_t d0 = 0; d0 < D; d0 += kUpload) {
         UploadArgs u{};
         u.d0 = d0;

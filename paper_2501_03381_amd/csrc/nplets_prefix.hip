@@ -327,7 +327,7 @@ __global__ __launch_bounds__(kPfxThreads) void k_eval_prefix(EvalArgs a, PfxTabl
     RedLds Rl = red_view(smem + pfx_stage_bytes(N, sizeof(F)), red.topk, red.bins);
     if (threadIdx.x == 0) bias_for(a.bias, k, sbias[0], sbias[1], sbias[2]);
     stage_corr<F>(a.Sigma + (int64_t)d * N * N, N, sR, sIsd, sLogd);
-    if constexpr (RED) red_begin(Rl, red.topk, red.bins);
+    if constexpr (RED) red_begin(Rl, red, d, k);
     const int S = k >= 4 ? 3 : 2;
     for (int64_t vb = vb0; vb < nblk; vb += nphys) {
         // the prefixes' last variable q: the blocks of each q in turn (4 units of 64 prefixes x

@@ -221,7 +221,7 @@ __global__ __launch_bounds__(kPairThreads, 4) void k_eval_pair(EvalArgs a, Piece
     RedLds S = red_view(smem + w2_stage_bytes(N, RED), red.topk, red.bins);
     if (threadIdx.x == 0) bias_for(a.bias, k, sbias[0], sbias[1], sbias[2]);
     stage_corr<double>(a.Sigma + (int64_t)d * N * N, N, sR, sIsd, sLogd);
-    if constexpr (RED) red_begin(S, red.topk, red.bins);
+    if constexpr (RED) red_begin(S, red, d, k);
     __syncthreads();
 
     const int q = threadIdx.x >> 5, i = threadIdx.x & 31, h = q & 1;

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kObjTile) void k_objective(const void* __restrict__
     const VT* v = static_cast<const VT*>(vals);
     __shared__ __align__(16) unsigned char sred[red_lds_bytes(kRedMaxK, kRedMaxBins)];
     RedLds S = red_view(sred, red.topk, red.bins);
-    if constexpr (RED) red_begin(S, red.topk, red.bins);
+    if constexpr (RED) red_begin(S, red, 0, 0);
     const int64_t b0 = (int64_t)blockIdx.x * per_blk;
     const int64_t b1 = min(B, b0 + per_blk);
     for (int64_t t = b0; t < b1; t += kObjTile) {          // uniform trip count in the workgroup
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(kObjTile) void k_objective(const void* __restrict__
 }
 
 struct ObjWs {
-    size_t key_off, g_off, hdr_off, total;
+    size_t key_off, g_off, hdr_off, bound_off, clear_end, total;
     int64_t blocks, per_blk;
 };
 
@@ -70,6 +70,11 @@ ObjWs obj_layout(int64_t B, int topk)
     w.per_blk = (tpb > 0 ? tpb : 1) * kObjTile;
     w.blocks = (B + w.per_blk - 1) / w.per_blk;
     size_t off = kWsHeader;
+    if (topk > 0) {
+        w.bound_off = off;             // admission bounds of the one list pair, cleared with the header
+        off = align_up(off + 16, 256);
+    }
+    w.clear_end = off;
     if (topk > 0) {
         const size_t segs = (size_t)(w.blocks > 0 ? w.blocks : 1);
         w.key_off = off; off = align_up(off + segs * 2 * topk * 8, 256);
@@ -94,7 +99,7 @@ thoi_status launch_objective(const void* vals, int32_t val_dtype, int64_t D, int
     const ObjWs w = obj_layout(B, red ? red->topk : 0);
     char* base = static_cast<char*>(ws);
     WsHeader* hdr = reinterpret_cast<WsHeader*>(base);
-    hipLaunchKernelGGL(k_ws_clear, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t*>(base), (int64_t)(kWsHeader / 4));
+    ws_clear(base, w.clear_end, s);
     RedArgs ra{};
     if (red) {
         ra.active = 1;
@@ -109,6 +114,7 @@ thoi_status launch_objective(const void* vals, int32_t val_dtype, int64_t D, int
             ra.seg_g = reinterpret_cast<int64_t*>(base + w.g_off);
             ra.seg_hdr = reinterpret_cast<SegHdr*>(base + w.hdr_off);
             ra.seg_cap = (uint32_t)(w.blocks > 0 ? w.blocks : 1);
+            ra.bound = reinterpret_cast<unsigned long long*>(base + w.bound_off);
         }
         ra.seg_next = &hdr->seg_next;
         ra.late_next = &hdr->late_next;

@@ -190,6 +190,24 @@ def test_reduce_refined_values_enter(env):
         check_hist(h[0, k], ref[2][sel], -3.0, 3.0, 20, 1e-3, f"k={k}")
 
 
+def test_reduce_list_sizes_exact(env):
+    """K = 1, one wavefront's worth (64), one past it and the maximum (256): the per-wavefront
+    lists are merged in blocks of 64 outputs, and the admission bounds shared between workgroups
+    drop values early; the selection must stay exact on the FP32 and FP64 paths."""
+    torch, api, B, synth, orc = env
+    S = orc.gc_covariance(synth.latent_20(T=3000))
+    Sd = dev(torch, S)
+    idx = orc.enumerate_nplets(20, 3, 20)
+    ords = orders_of(idx)
+    for prec in ("fp32_refine", "fp64"):
+        out, _ = api.nplets_measures(Sd, orders=(3, 20), precision=prec, out_dtype=torch.float64)
+        om = out[2].cpu().numpy()
+        for K in (1, 64, 65, 256):
+            say(f"reduce {prec} N=20 orders 3..20 topk={K}")
+            tv, tg, _ = api.nplets_reduce(Sd, orders=(3, 20), topk=K, precision=prec).result()
+            check_lists(tv[0], tg[0], om, ords, K, 0.0)
+
+
 def test_reduce_many_datasets(env):
     torch, api, B, synth, orc = env
     Xs = synth.replicas_20(3, T=2000)
