@@ -20,7 +20,7 @@ constexpr int kSortThreads = 1024;
 constexpr int kSortReg = kChunk / kSortThreads;    // elements per thread in the sort (one)
 constexpr int kMergeThreads = 1024;
 constexpr int kMergeReg = kChunk / kMergeThreads;  // elements per thread in the merge
-constexpr int kMergeStage = 7;                     // chunks staged in LDS at a time (56 KB of values)
+constexpr int kMergeStage = 16;                    // chunks staged in LDS at a time (128 KB of values)
 
 // Monotone map of a double onto uint64 (total order; -0.0 is folded onto +0.0).
 __device__ __forceinline__ uint64_t order_key(double x)
@@ -207,10 +207,10 @@ __global__ __launch_bounds__(kMergeThreads) void k_copula_merge(int64_t T, int64
     const int64_t c = cd % N, d = cd / N;
     const int64_t col = (d * N + c) * nchunks;
     const int nq = (int)min<int64_t>(kChunk, T - (int64_t)q * kChunk);
+    // the flags, the thread's own entries and the first stage's chunks are loaded together
     int f = 0;
     for (int o = tid; o < nchunks; o += kMergeThreads) f |= nanflag[col + o];
-    const bool bad = __syncthreads_or(f) != 0;
-    if (bad && q == 0 && tid == 0) raise_status(hdr, THOI_EINVAL_DATA);
+    bool bad = false;
 
     const int p0 = tid * kMergeReg;
     uint64_t mk[kMergeReg];
@@ -223,27 +223,30 @@ __global__ __launch_bounds__(kMergeThreads) void k_copula_merge(int64_t T, int64
         rank[e] = p0 + e;                                  // entries of its own chunk before it
     }
     for (int o0 = 0; o0 < nchunks; o0 += kMergeStage) {
-        // stage chunks o0 .. o0+kMergeStage-1; missing chunks and chunk q itself read as sentinels
-        // (larger than every value, so they count nothing)
+        // stage chunks o0 .. o0+kMergeStage-1 other than q; slots past the last chunk and chunk q
+        // itself are neither loaded nor searched (uniform branches)
         uint64_t lk[kMergeStage][kChunk / kMergeThreads];
 #pragma unroll
         for (int s = 0; s < kMergeStage; ++s) {
-            const bool use = o0 + s < nchunks && o0 + s != q;
-            const int64_t src = (col + (use ? o0 + s : q)) * (int64_t)kChunk;
+            if (o0 + s < nchunks && o0 + s != q) {
+                const int64_t src = (col + o0 + s) * (int64_t)kChunk;
 #pragma unroll
-            for (int e = 0; e < kChunk / kMergeThreads; ++e) {
-                const uint64_t v = wkey[src + e * kMergeThreads + tid];
-                lk[s][e] = use ? v : ~0ull;
+                for (int e = 0; e < kChunk / kMergeThreads; ++e) lk[s][e] = wkey[src + e * kMergeThreads + tid];
             }
         }
-        __syncthreads();                           // the previous stage's searches are done
+        if (o0 == 0) bad = __syncthreads_or(f) != 0;     // uniform
+        else __syncthreads();                      // the previous stage's searches are done
 #pragma unroll
-        for (int s = 0; s < kMergeStage; ++s)
+        for (int s = 0; s < kMergeStage; ++s) {
+            if (o0 + s < nchunks && o0 + s != q) {
 #pragma unroll
-            for (int e = 0; e < kChunk / kMergeThreads; ++e) okey[s][e * kMergeThreads + tid] = lk[s][e];
+                for (int e = 0; e < kChunk / kMergeThreads; ++e) okey[s][e * kMergeThreads + tid] = lk[s][e];
+            }
+        }
         __syncthreads();
 #pragma unroll
         for (int s = 0; s < kMergeStage; ++s) {
+            if (o0 + s >= nchunks || o0 + s == q) continue;
             const bool le = o0 + s < q;           // equal values of an earlier chunk come first
 #pragma unroll
             for (int e = 0; e < kMergeReg; ++e) {
@@ -261,6 +264,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_copula_merge(int64_t T, int64
             }
         }
     }
+    if (bad && q == 0 && tid == 0) raise_status(hdr, THOI_EINVAL_DATA);
 #pragma unroll
     for (int e = 0; e < kMergeReg; ++e) {
         if (p0 + e < nq) {
