@@ -415,9 +415,9 @@ def bench_greedy(torch, np, api, B, synth, dev, args):
 
 def bench_anneal(torch, np, api, B, synth, dev, args):
     """Batched simulated annealing (Methods, "Heuristics") on the 100-variable concatenated PGM
-    within order 20: 1024 chains x 800 iterations, T0 = 0.2, alpha = 0.99, FP64 evaluation of each
-    iteration's 1024 proposals in one call.  The oracle's annealer runs beside it on 64 chains x 30
-    iterations."""
+    within order 20: 1024 chains x 800 iterations, T0 = 0.2, alpha = 0.99, the whole run on the
+    device (one launch per iteration: propose, FP64 evaluation, Metropolis decision).  The oracle's
+    annealer runs beside it on 64 chains x 30 iterations."""
     from paper_2501_03381_amd import search
     S = synth.concatenated_100()
     Sd = torch.from_numpy(S).to(dev)

@@ -294,6 +294,34 @@ thoi_status thoi_objective(const void* vals, int32_t val_dtype, int64_t D, int64
                            const thoi_reduce* red, void* ws, size_t ws_bytes, void* stream);
 size_t thoi_objective_workspace_bytes(int64_t D, int64_t B, const thoi_reduce* red);
 
+/*
+ * Batched simulated annealing over n-plets, run on the device (Methods, "Heuristics", "Simulated
+ * Annealing Algorithm").  kappa chains, each an n-plet as a bit mask of the N <= 128 variables
+ * (two 64-bit words per chain: variable i is bit i % 64 of word i / 64), start from masks0.  Iteration t (t = 0 .. iters-1), per chain c:
+ *   neighbour: within an order (across = 0) the floor(a k)-th member (ascending) is swapped for the
+ *     floor(b (N - k))-th outsider; across orders (across = 1) the n-plet instead gains that
+ *     outsider when move < 1/3 and k < k_max, or loses that member when 1/3 <= move < 2/3 and
+ *     k > k_min, and is swapped otherwise (k = order of the current n-plet; a, b, move are
+ *     draw_a, draw_b, draw_move [t][c]);
+ *   energy E = Omega (maximize != 0) or -Omega; dE = E(neighbour) - E(current); the neighbour is
+ *     taken when dE > 0 or draw_accept[t][c] < exp(dE / temp_t), and never when it is not positive
+ *     definite (its Omega is NaN); temp_0 = T0 and temp_{t+1} = temp_t * alpha;
+ *   the best state seen so far is kept (a later state replaces it only with a strictly larger E).
+ * Omega is evaluated in FP64 from the correlation of Sigma (N x N, device, row-major).
+ *   masks0: device [kappa][2] uint64; orders in [k_min, k_max]; bits at N and above are ignored.
+ *   draw_*: device [iters][kappa] FP64 in [0, 1); draw_move is needed only when across = 1.
+ *   cur_mask, best_mask: device [kappa][2] uint64; cur_omega, best_omega: device [kappa] FP64;
+ *     accepted: device [kappa] int64 (the final state, the best state and the number of accepted
+ *     moves per chain).
+ * 1 <= k_min <= k_max <= min(N - 1, 64); T0 > 0, alpha > 0.  Every iteration is one kernel launch on
+ * `stream`; nothing is allocated and the host does not wait.
+ */
+thoi_status thoi_anneal(const double* Sigma, int32_t N, const uint64_t* masks0, int32_t kappa, int32_t iters,
+                        const double* draw_move, const double* draw_a, const double* draw_b, const double* draw_accept,
+                        double T0, double alpha, int32_t maximize, int32_t across, int32_t k_min, int32_t k_max,
+                        uint64_t* cur_mask, double* cur_omega, uint64_t* best_mask, double* best_omega,
+                        int64_t* accepted, void* stream);
+
 /* Initialise reducer arrays for D datasets (top_g = -1, hist = 0). */
 thoi_status thoi_reduce_init(const thoi_reduce* red, int64_t D, int32_t kmax, void* stream);
 

@@ -36,7 +36,7 @@ EXPORTS = [
     "thoi_workspace_bytes", "thoi_ws_status_offset", "thoi_count", "thoi_unrank_host", "thoi_bias_offsets",
     "thoi_status_string", "thoi_version", "thoi_nplets_eval_multi", "thoi_multi_offsets",
     "thoi_multi_workspace_bytes", "thoi_objective", "thoi_objective_workspace_bytes", "thoi_eval_launch_shape",
-    "thoi_nplets_eval_noalloc",
+    "thoi_nplets_eval_noalloc", "thoi_anneal",
 ]
 
 
@@ -126,11 +126,13 @@ def lib():
     L.thoi_objective_workspace_bytes.argtypes = [I64, I64, ctypes.POINTER(ThoiReduce)]
     L.thoi_objective_workspace_bytes.restype = SZ
     L.thoi_eval_launch_shape.argtypes = [I32, NP, OP, ctypes.POINTER(I32), ctypes.POINTER(I64)]
+    D = ctypes.c_double
+    L.thoi_anneal.argtypes = [P, I32, P, I32, I32, P, P, P, P, D, D, I32, I32, I32, I32, P, P, P, P, P, P]
     L.thoi_version.argtypes = []
     L.thoi_version.restype = ctypes.c_char_p
     for fn in ("thoi_copulize", "thoi_cov", "thoi_nplets_eval", "thoi_nplets_eval_backward", "thoi_reduce_init",
                "thoi_unrank_host", "thoi_bias_offsets", "thoi_nplets_eval_multi", "thoi_multi_offsets",
-               "thoi_objective", "thoi_eval_launch_shape", "thoi_nplets_eval_noalloc"):
+               "thoi_objective", "thoi_eval_launch_shape", "thoi_nplets_eval_noalloc", "thoi_anneal"):
         getattr(L, fn).restype = I32
     _lib = L
     return L
@@ -194,6 +196,13 @@ def thoi_objective(vals, val_dtype, D, B, kind, obj, red, ws, ws_bytes, stream):
     check("thoi_objective", lib().thoi_objective(vals, val_dtype, D, B, kind, obj,
                                                  ctypes.byref(red) if red is not None else None, ws, ws_bytes,
                                                  stream))
+
+
+def thoi_anneal(Sigma, N, masks0, kappa, iters, move, a, b, accept, T0, alpha, maximize, across, k_min, k_max,
+                cur_mask, cur_omega, best_mask, best_omega, accepted, stream):
+    check("thoi_anneal", lib().thoi_anneal(Sigma, N, masks0, kappa, iters, move, a, b, accept, T0, alpha, maximize,
+                                           across, k_min, k_max, cur_mask, cur_omega, best_mask, best_omega,
+                                           accepted, stream))
 
 
 def thoi_objective_workspace_bytes(D, B, red=None) -> int:

@@ -357,6 +357,24 @@ thoi_status thoi_objective(const void* vals, int32_t val_dtype, int64_t D, int64
     return launch_objective(vals, val_dtype, D, B, kind, obj, red, ws, (hipStream_t)stream);
 }
 
+thoi_status thoi_anneal(const double* Sigma, int32_t N, const uint64_t* masks0, int32_t kappa, int32_t iters,
+                        const double* draw_move, const double* draw_a, const double* draw_b, const double* draw_accept,
+                        double T0, double alpha, int32_t maximize, int32_t across, int32_t k_min, int32_t k_max,
+                        uint64_t* cur_mask, double* cur_omega, uint64_t* best_mask, double* best_omega,
+                        int64_t* accepted, void* stream)
+{
+    if (N < 2 || N > 128 || kappa < 1 || iters < 0) return THOI_EINVAL;
+    if (kappa > (1 << 20) || (int64_t)iters * kappa > ((int64_t)1 << 40)) return THOI_EUNSUPPORTED;
+    if (k_min < 1 || k_min > k_max || k_max > N - 1) return THOI_EINVAL;
+    if (k_max > 64) return THOI_EUNSUPPORTED;
+    if (!(T0 > 0.0) || !std::isfinite(T0) || !(alpha > 0.0) || !std::isfinite(alpha)) return THOI_EINVAL;
+    if (!Sigma || !masks0 || !cur_mask || !cur_omega || !best_mask || !best_omega || !accepted) return THOI_EINVAL;
+    if (iters > 0 && (!draw_a || !draw_b || !draw_accept || (across && !draw_move))) return THOI_EINVAL;
+    return launch_anneal(Sigma, N, masks0, kappa, iters, draw_move, draw_a, draw_b, draw_accept, T0, alpha, maximize,
+                         across, k_min, k_max, cur_mask, cur_omega, best_mask, best_omega, accepted,
+                         (hipStream_t)stream);
+}
+
 size_t thoi_objective_workspace_bytes(int64_t D, int64_t B, const thoi_reduce* red)
 {
     return (D >= 1 && B >= 0) ? objective_ws_bytes(D, B, red) : 0;

@@ -350,17 +350,12 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-__device__ __forceinline__ FactorOut<double> wave_factor(const double* __restrict__ sR, int N, const int* __restrict__ cidx,
-                                                         int k, double* __restrict__ sM, int ks,
-                                                         double* __restrict__ sInv)
+// Factorisation of the k x k block already gathered into the lower triangle of sM (row stride
+// ks, unit diagonal), one wavefront: log det, sum of log a_j and max a_j.
+__device__ __forceinline__ FactorOut<double> wave_factor_core(int k, double* __restrict__ sM, int ks,
+                                                              double* __restrict__ sInv)
 {
     const int lane = threadIdx.x & 63;
-    if (lane < k) {
-        const double* row = sR + cidx[lane] * N;
-        for (int j = 0; j < lane; ++j) sM[lane * ks + j] = row[cidx[j]];
-        sM[lane * ks + lane] = 1.0;
-    }
-    __syncthreads();
     bool ok = true;
     double lp = 0.0;   // this lane's log pivot (lane j holds log L_jj^2)
     for (int j = 0; j < k; ++j) {
@@ -399,6 +394,20 @@ __device__ __forceinline__ FactorOut<double> wave_factor(const double* __restric
     o.ok = ok;
     __syncthreads();
     return o;
+}
+
+__device__ __forceinline__ FactorOut<double> wave_factor(const double* __restrict__ sR, int N, const int* __restrict__ cidx,
+                                                         int k, double* __restrict__ sM, int ks,
+                                                         double* __restrict__ sInv)
+{
+    const int lane = threadIdx.x & 63;
+    if (lane < k) {
+        const double* row = sR + cidx[lane] * N;
+        for (int j = 0; j < lane; ++j) sM[lane * ks + j] = row[cidx[j]];
+        sM[lane * ks + lane] = 1.0;
+    }
+    __syncthreads();
+    return wave_factor_core(k, sM, ks, sInv);
 }
 
 }  // namespace thoi

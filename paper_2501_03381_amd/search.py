@@ -213,7 +213,7 @@ def _omega_masks(S: torch.Tensor, masks: np.ndarray, precision: str) -> np.ndarr
 
 def anneal(Sigma: torch.Tensor, masks0: np.ndarray, draws: dict, T0: float = 1.0, alpha: float = 0.99,
            maximize: bool = True, mode: str = "within", k_min: int = 3, k_max: int | None = None,
-           precision: str = "fp64"):
+           precision: str = "fp64", on_device: bool | None = None):
     """Batched simulated annealing (Methods, "Heuristics", "Simulated Annealing Algorithm").
 
     kappa chains start from masks0 [kappa][N] (orders may differ: one call evaluates the mixed
@@ -224,6 +224,11 @@ def anneal(Sigma: torch.Tensor, masks0: np.ndarray, draws: dict, T0: float = 1.0
     starts at T0 and is multiplied by alpha each iteration.  Proposals that are not positive
     definite are rejected.  Returns (best masks, best Omega, final masks, final Omega, accepted
     count per chain).
+
+    on_device (default: with precision "fp64", N <= 128 and orders <= 64): the whole run goes to
+    the device in one call (thoi_anneal: one kernel launch per iteration, no host round trip);
+    otherwise every iteration evaluates its proposals with one batched evaluator call and decides
+    on the host.
     """
     if mode not in ("within", "across"):
         raise ValueError("mode is 'within' or 'across'")
@@ -235,6 +240,13 @@ def anneal(Sigma: torch.Tensor, masks0: np.ndarray, draws: dict, T0: float = 1.0
     if k_max > N - 1 or k_min < 1 or ks.min() < k_min or ks.max() > k_max:
         raise ValueError("need 1 <= k_min <= every initial order <= k_max <= N - 1")
     sign = 1.0 if maximize else -1.0
+    if on_device is None:
+        on_device = (precision == "fp64" and N <= 128 and ks.max() <= 64 and (mode == "within" or k_max <= 64)
+                     and T0 > 0 and alpha > 0)
+    if on_device:
+        # within an order the bounds only matter to the validation: clamp them to the kernel's range
+        kx = min(k_max, 64)
+        return _anneal_device(S, cur, draws, T0, alpha, maximize, mode, min(k_min, kx), kx)
     om = _omega_masks(S, cur, precision)
     E = sign * om
     best, Ebest = cur.copy(), E.copy()
@@ -254,6 +266,41 @@ def anneal(Sigma: torch.Tensor, masks0: np.ndarray, draws: dict, T0: float = 1.0
         best[better], Ebest[better] = cur[better], E[better]
         temp *= alpha
     return best, sign * Ebest, cur, sign * E, accepted
+
+
+def _anneal_device(S: torch.Tensor, cur: np.ndarray, draws: dict, T0: float, alpha: float, maximize: bool,
+                   mode: str, k_min: int, k_max: int):
+    kappa, N = cur.shape
+    dev = S.device
+    Sd = S.to(torch.float64).contiguous()
+    words = np.zeros((kappa, 2), dtype=np.uint64)
+    for h in range(2):
+        part = cur[:, 64 * h: 64 * (h + 1)]
+        words[:, h] = (part.astype(np.uint64) << np.arange(part.shape[1], dtype=np.uint64)[None, :]).sum(
+            1, dtype=np.uint64)
+    m0 = torch.from_numpy(words.view(np.int64).copy()).to(dev)
+    iters = int(draws["accept"].shape[0])
+
+    def rows(name):
+        x = np.ascontiguousarray(np.asarray(draws[name], dtype=np.float64)[:iters].reshape(iters, kappa))
+        return torch.from_numpy(x).to(dev)
+    across = mode == "across"
+    dm = rows("move") if across else None
+    da, db, du = rows("a"), rows("b"), rows("accept")
+    cm = torch.empty((kappa, 2), dtype=torch.int64, device=dev)
+    bm = torch.empty_like(cm)
+    co = torch.empty(kappa, dtype=torch.float64, device=dev)
+    bo = torch.empty_like(co)
+    acc = torch.empty(kappa, dtype=torch.int64, device=dev)
+    B.thoi_anneal(api._ptr(Sd), N, api._ptr(m0), kappa, iters, api._ptr(dm), api._ptr(da), api._ptr(db),
+                  api._ptr(du), float(T0), float(alpha), 1 if maximize else 0, 1 if across else 0, k_min, k_max,
+                  api._ptr(cm), api._ptr(co), api._ptr(bm), api._ptr(bo), api._ptr(acc), api._stream(dev))
+
+    def unpack(t):
+        v = t.cpu().numpy().view(np.uint64)
+        i = np.arange(N)
+        return ((v[:, i // 64] >> (i % 64).astype(np.uint64)[None, :]) & np.uint64(1)).astype(bool)
+    return unpack(bm), bo.cpu().numpy(), unpack(cm), co.cpu().numpy(), acc.cpu().numpy()
 
 
 # ------------------------------------------------------------------------------------------------ across datasets

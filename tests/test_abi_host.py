@@ -224,6 +224,30 @@ def test_objective_argument_errors(B):
     assert need > B.thoi_objective_workspace_bytes(4, 100000, None) >= 256
 
 
+def test_anneal_argument_errors(B):
+    """thoi_anneal rejects bad shapes, bounds, schedules and missing arrays before any launch."""
+    L = B.lib()
+    f = ctypes.c_void_p(0x1000)
+
+    def call(N=20, kappa=8, iters=5, move=f, a=f, b=f, u=f, T0=1.0, alpha=0.9, across=1, kmin=3, kmax=10, out=f):
+        return L.thoi_anneal(f, N, f, kappa, iters, move, a, b, u, T0, alpha, 1, across, kmin, kmax, out, f, f, f, f,
+                             None)
+    assert call(N=1) == B.THOI_EINVAL
+    assert call(N=129) == B.THOI_EINVAL
+    assert call(kappa=0) == B.THOI_EINVAL
+    assert call(iters=-1) == B.THOI_EINVAL
+    assert call(kmin=0) == B.THOI_EINVAL
+    assert call(kmin=11, kmax=10) == B.THOI_EINVAL
+    assert call(kmax=20) == B.THOI_EINVAL                 # an order-N n-plet has no outsider to swap in
+    assert call(N=100, kmax=65) == B.THOI_EUNSUPPORTED    # one wavefront factors orders up to 64
+    assert call(T0=0.0) == B.THOI_EINVAL
+    assert call(alpha=float("nan")) == B.THOI_EINVAL
+    assert call(move=None) == B.THOI_EINVAL               # across orders needs the move draws
+    assert call(u=None) == B.THOI_EINVAL
+    assert call(out=None) == B.THOI_EINVAL
+    assert call(kappa=1 << 21) == B.THOI_EUNSUPPORTED
+
+
 def test_launch_plan_stays_below_dispatch_limit(B):
     """Every engine grid stays below 2^30 work-items along x (the dispatch limit is 2^32), also for
     enumerations whose one-workgroup-per-n-plet wave grid would exceed it: FP64 orders 19..30 at

@@ -149,6 +149,28 @@ def test_anneal_matches_oracle(env, mode):
         assert np.abs(vb - np.array(rvb)).max() < 1e-9 and np.abs(vc - np.array(rvc)).max() < 1e-9
 
 
+def test_anneal_device_matches_host_loop_wide(env):
+    """The device annealer (one launch per iteration, two-word masks above 64 variables) against
+    the host-driven loop over the batched evaluator, on the 100-variable latent model (sampled
+    data: no two n-plets share an Omega exactly, so both loops take the same decisions): the same
+    states, best states and acceptance counts, values within 1e-9, in both modes."""
+    torch, search, osearch, synth, orc = env
+    S = orc.gc_covariance(synth.latent_100()[0])
+    m0 = synth.sa_initial(41, 24, 100, 18, 22)
+    dr = synth.sa_draws(42, 40, 24)
+    for mode in ("within", "across"):
+        for maximize in (True, False):
+            say(f"anneal N=100 kappa 24 x 40 mode={mode} maximize={maximize}: device vs host loop")
+            kw = dict(T0=0.2, alpha=0.97, maximize=maximize, mode=mode, k_min=16, k_max=24)
+            got = search.anneal(dev(torch, S), m0, dr, on_device=True, **kw)
+            ref = search.anneal(dev(torch, S), m0, dr, on_device=False, **kw)
+            for x, y in ((got[0], ref[0]), (got[2], ref[2])):
+                assert np.array_equal(x, y)
+            assert np.array_equal(got[4], ref[4])
+            assert np.abs(got[1] - ref[1]).max() < 1e-9 and np.abs(got[3] - ref[3]).max() < 1e-9
+            assert got[4].sum() > 0
+
+
 def test_anneal_pgm_blocks(env):
     torch, search, osearch, synth, orc = env
     S = synth.block_diag(synth.r_system(5, 1.0), synth.s_system(5, 1.0), np.eye(6))
