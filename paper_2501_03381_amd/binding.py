@@ -36,7 +36,7 @@ EXPORTS = [
     "thoi_workspace_bytes", "thoi_ws_status_offset", "thoi_count", "thoi_unrank_host", "thoi_bias_offsets",
     "thoi_status_string", "thoi_version", "thoi_nplets_eval_multi", "thoi_multi_offsets",
     "thoi_multi_workspace_bytes", "thoi_objective", "thoi_objective_workspace_bytes", "thoi_eval_launch_shape",
-    "thoi_nplets_eval_noalloc", "thoi_anneal",
+    "thoi_nplets_eval_noalloc", "thoi_anneal", "thoi_greedy", "thoi_greedy_workspace_bytes",
 ]
 
 
@@ -128,11 +128,14 @@ def lib():
     L.thoi_eval_launch_shape.argtypes = [I32, NP, OP, ctypes.POINTER(I32), ctypes.POINTER(I64)]
     D = ctypes.c_double
     L.thoi_anneal.argtypes = [P, I32, P, I32, I32, P, P, P, P, D, D, I32, I32, I32, I32, P, P, P, P, P, P]
+    L.thoi_greedy.argtypes = [P, I32, I32, I32, I32, I32, P, P, P, P, SZ, P]
+    L.thoi_greedy_workspace_bytes.argtypes = [I32, I32]
+    L.thoi_greedy_workspace_bytes.restype = SZ
     L.thoi_version.argtypes = []
     L.thoi_version.restype = ctypes.c_char_p
     for fn in ("thoi_copulize", "thoi_cov", "thoi_nplets_eval", "thoi_nplets_eval_backward", "thoi_reduce_init",
                "thoi_unrank_host", "thoi_bias_offsets", "thoi_nplets_eval_multi", "thoi_multi_offsets",
-               "thoi_objective", "thoi_eval_launch_shape", "thoi_nplets_eval_noalloc", "thoi_anneal"):
+               "thoi_objective", "thoi_eval_launch_shape", "thoi_nplets_eval_noalloc", "thoi_anneal", "thoi_greedy"):
         getattr(L, fn).restype = I32
     _lib = L
     return L
@@ -203,6 +206,15 @@ def thoi_anneal(Sigma, N, masks0, kappa, iters, move, a, b, accept, T0, alpha, m
     check("thoi_anneal", lib().thoi_anneal(Sigma, N, masks0, kappa, iters, move, a, b, accept, T0, alpha, maximize,
                                            across, k_min, k_max, cur_mask, cur_omega, best_mask, best_omega,
                                            accepted, stream))
+
+
+def thoi_greedy(Sigma, N, k_first, steps, kappa, maximize, sols, vals, count, ws, ws_bytes, stream):
+    check("thoi_greedy", lib().thoi_greedy(Sigma, N, k_first, steps, kappa, maximize, sols, vals, count, ws, ws_bytes,
+                                           stream))
+
+
+def thoi_greedy_workspace_bytes(N, kappa) -> int:
+    return int(lib().thoi_greedy_workspace_bytes(N, kappa))
 
 
 def thoi_objective_workspace_bytes(D, B, red=None) -> int:

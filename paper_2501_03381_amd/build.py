@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libthoi.so")
 SOURCES = ["nplets_bwd_lane_hi.hip", "nplets_bwd_lane_lo.hip", "nplets_fwd.hip", "nplets_prefix.hip", "nplets_wave2.hip", "nplets_multi.hip",
            "api.cpp", "fan.cpp",
            "copula.hip", "cov.hip", "nplets_bwd.hip",
-           "objective.hip", "noalloc.hip", "nplets_anneal.hip"]
+           "objective.hip", "noalloc.hip", "nplets_anneal.hip", "nplets_greedy.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", CSRC, "-I", INCLUDE,

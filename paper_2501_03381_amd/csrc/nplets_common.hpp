@@ -351,9 +351,11 @@ __device__ __forceinline__ double wave_max(double v)
 }
 
 // Factorisation of the k x k block already gathered into the lower triangle of sM (row stride
-// ks, unit diagonal), one wavefront: log det, sum of log a_j and max a_j.
+// ks, unit diagonal), one wavefront: log det, sum of log a_j and max a_j.  With sSeq (128
+// doubles of LDS) the two sums are taken by lane 0 in variable order instead of by a lane tree, so
+// inserting an independent variable (a zero row and column) changes no bit of the result.
 __device__ __forceinline__ FactorOut<double> wave_factor_core(int k, double* __restrict__ sM, int ks,
-                                                              double* __restrict__ sInv)
+                                                              double* __restrict__ sInv, double* __restrict__ sSeq = nullptr)
 {
     const int lane = threadIdx.x & 63;
     bool ok = true;
@@ -388,8 +390,19 @@ __device__ __forceinline__ FactorOut<double> wave_factor_core(int k, double* __r
         la = log(acc);
     }
     FactorOut<double> o;
-    o.ld = wave_sum(lane < k ? lp : 0.0);
-    o.sa = wave_sum(la);
+    if (sSeq) {
+        if (lane < k) { sSeq[lane] = lp; sSeq[64 + lane] = la; }
+        __syncthreads();
+        double s1 = 0.0, s2 = 0.0;
+        if (lane == 0) {
+            for (int j = 0; j < k; ++j) { s1 += sSeq[j]; s2 += sSeq[64 + j]; }
+        }
+        o.ld = __shfl(s1, 0, 64);
+        o.sa = __shfl(s2, 0, 64);
+    } else {
+        o.ld = wave_sum(lane < k ? lp : 0.0);
+        o.sa = wave_sum(la);
+    }
     o.vmax = wave_max(acc);
     o.ok = ok;
     __syncthreads();

@@ -1,0 +1,204 @@
+// Greedy growth run on the device (Methods, "Heuristics", "Greedy Algorithm"): from the kappa
+// best n-plets of one order, every solution is extended by every variable it lacks, all
+// candidates of the next order are evaluated, and the kappa best are kept; the orders follow one
+// another with no host round trip (two launches per order).
+//
+// Candidate (p, v) is solution p extended by variable v.  A candidate reached from several parents
+// is evaluated once, from the first of them (the lowest p whose solution is a subset of it).  One
+// 64-lane workgroup per candidate factors its correlation block (FP64), taking the sums of the
+// logs in variable order, so candidates that differ only by which independent variable they hold
+// get bit-identical values.  One workgroup then sorts every candidate of the order by the
+// objective and, among equal values, by the n-plet in lexicographic order (the smaller first), and
+// keeps the first kappa.
+#include "thoi_internal.hpp"
+#include "nplets_common.hpp"
+
+namespace thoi {
+namespace {
+
+constexpr int kGreedyKs = 64;
+constexpr int kSelThreads = 1024;
+constexpr int kSelMax = 4096;           // candidates of one order that the selection sorts in LDS
+
+struct Mask {
+    uint64_t w[2];
+};
+
+__device__ __forceinline__ int popc(const Mask& m) { return __popcll(m.w[0]) + __popcll(m.w[1]); }
+
+__device__ __forceinline__ bool has(const Mask& m, int v) { return (m.w[v >> 6] >> (v & 63)) & 1ull; }
+
+__device__ __forceinline__ bool subset(const Mask& a, const Mask& b)
+{
+    return (a.w[0] & ~b.w[0]) == 0 && (a.w[1] & ~b.w[1]) == 0;
+}
+
+// a before b in lexicographic order of the sorted index tuples (equal orders): the lowest variable
+// in which they differ belongs to a
+__device__ __forceinline__ bool lex_less(const Mask& a, const Mask& b)
+{
+    const uint64_t x0 = a.w[0] ^ b.w[0];
+    if (x0) return (a.w[0] >> __builtin_ctzll(x0)) & 1ull;
+    const uint64_t x1 = a.w[1] ^ b.w[1];
+    if (x1) return (a.w[1] >> __builtin_ctzll(x1)) & 1ull;
+    return false;
+}
+
+// total order on doubles as uint64 (-0.0 folded onto +0.0)
+__device__ __forceinline__ uint64_t okey(double x)
+{
+    if (x == 0.0) x = 0.0;
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
+struct GreedyArgs {
+    const double* Sigma;
+    int N;
+    int kappa;
+    double sign;            // +1: keep the largest Omega, -1: the smallest
+    Mask* sols;             // [steps + 1][kappa]; slot 0 holds the first order's solutions
+    double* vals;           // [steps + 1][kappa]
+    int32_t* count;         // [steps + 1]
+    Mask* cmask;            // [kappa * N] candidates of the current step
+    double* com;            // [kappa * N] their Omega (NaN: not a candidate or not positive definite)
+};
+
+// grid (kappa * N), block 64: candidate (p, v) = blockIdx.x / N, % N of step s (order k + 1).
+__global__ __launch_bounds__(64) void k_greedy_eval(GreedyArgs g, int s)
+{
+    __shared__ double sM[64 * kGreedyKs];
+    __shared__ double sInv[64], sIsd[64], sSeq[128];
+    __shared__ int cidx[64];
+    const int N = g.N;
+    const int p = blockIdx.x / N, v = blockIdx.x % N;
+    const int lane = threadIdx.x;
+    const int64_t slot = blockIdx.x;
+    const int cnt = g.count[s];
+    const Mask* sol = g.sols + (int64_t)s * g.kappa;
+    // uniform in the workgroup: a parent that exists, a variable it lacks, and no earlier parent
+    // reaching the same n-plet
+    bool use = p < cnt && !has(sol[p], v);
+    Mask C{};
+    if (use) {
+        C = sol[p];
+        C.w[v >> 6] |= 1ull << (v & 63);
+        for (int q = lane; q < p; q += 64) use = use && !subset(sol[q], C);
+        use = __all(use);                      // __all over the wavefront: every earlier parent checked
+    }
+    if (!use) {
+        if (lane == 0) g.com[slot] = __builtin_nan("");
+        return;
+    }
+    int k = popc(C);
+    k = k < 64 ? k : 64;
+    int ci = 0;
+    if (lane < k) {
+        // lane j takes the (j+1)-th member
+        Mask m = C;
+        int n = lane;
+        ci = 0;
+        for (int h = 0; h < 2; ++h) {
+            const int c = __popcll(m.w[h]);
+            if (n < c) {
+                uint64_t x = m.w[h];
+                for (int i = 0; i < n; ++i) x &= x - 1;
+                ci = 64 * h + __builtin_ctzll(x);
+                break;
+            }
+            n -= c;
+        }
+        cidx[lane] = ci;
+        const double dj = g.Sigma[(int64_t)ci * N + ci];
+        sIsd[lane] = dj > 0.0 ? 1.0 / sqrt(dj) : __builtin_nan("");
+    }
+    __syncthreads();
+    if (lane < k) {
+        const double* row = g.Sigma + (int64_t)ci * N;
+        const double si = sIsd[lane];
+        for (int j = 0; j < lane; ++j) sM[lane * kGreedyKs + j] = row[cidx[j]] * si * sIsd[j];
+        sM[lane * kGreedyKs + lane] = 1.0;
+    }
+    __syncthreads();
+    const FactorOut<double> f = wave_factor_core(k, sM, kGreedyKs, sInv, sSeq);
+    if (lane == 0) {
+        const bool ok = f.ok && isfinite(f.ld) && isfinite(f.sa);
+        const double TC = -0.5 * f.ld, DTC = 0.5 * (f.ld + f.sa);
+        g.cmask[slot] = C;
+        g.com[slot] = ok ? TC - DTC : __builtin_nan("");
+    }
+}
+
+// grid 1, block kSelThreads: sort the ncand = kappa * N slots of step s and keep the kappa best
+// distinct n-plets as step s + 1.
+__global__ __launch_bounds__(kSelThreads) void k_greedy_select(GreedyArgs g, int s)
+{
+    __shared__ uint64_t key[kSelMax];
+    __shared__ int idx[kSelMax];
+    const int ncand = g.kappa * g.N;
+    int P = 1;
+    while (P < ncand) P <<= 1;
+    for (int i = threadIdx.x; i < P; i += kSelThreads) {
+        const double o = i < ncand ? g.com[i] : __builtin_nan("");
+        // ascending key = better first; invalid slots last
+        key[i] = isnan(o) ? ~0ull : (g.sign > 0.0 ? ~okey(o) : okey(o));
+        idx[i] = i < ncand ? i : -1;
+    }
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < (P >> 1); i += kSelThreads) {
+                const int lo = 2 * i - (i & (stride - 1)), hi = lo + stride;
+                const bool asc = (lo & size) == 0;
+                const uint64_t ka = key[lo], kb = key[hi];
+                const int ia = idx[lo], ib = idx[hi];
+                // b before a: smaller key, or equal valid keys and the lexicographically smaller n-plet
+                bool b_first = kb < ka;
+                if (kb == ka && ka != ~0ull && ia >= 0 && ib >= 0) b_first = lex_less(g.cmask[ib], g.cmask[ia]);
+                if (b_first == asc) { key[lo] = kb; key[hi] = ka; idx[lo] = ib; idx[hi] = ia; }
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Mask* out = g.sols + (int64_t)(s + 1) * g.kappa;
+        double* ov = g.vals + (int64_t)(s + 1) * g.kappa;
+        int n = 0;
+        for (int i = 0; i < ncand && n < g.kappa; ++i) {
+            if (key[i] == ~0ull) break;
+            out[n] = g.cmask[idx[i]];
+            ov[n] = g.com[idx[i]];
+            ++n;
+        }
+        g.count[s + 1] = n;
+    }
+}
+
+}  // namespace
+
+size_t greedy_ws_bytes(int32_t N, int32_t kappa) { return (size_t)kappa * N * (sizeof(Mask) + 8) + 256; }
+
+int greedy_select_max() { return kSelMax; }
+
+thoi_status launch_greedy(const double* Sigma, int32_t N, int32_t kappa, int32_t steps, int32_t maximize,
+                          uint64_t* sols, double* vals, int32_t* count, void* ws, hipStream_t s)
+{
+    GreedyArgs g{};
+    g.Sigma = Sigma;
+    g.N = N;
+    g.kappa = kappa;
+    g.sign = maximize ? 1.0 : -1.0;
+    g.sols = reinterpret_cast<Mask*>(sols);
+    g.vals = vals;
+    g.count = count;
+    char* base = static_cast<char*>(ws);
+    g.cmask = reinterpret_cast<Mask*>(base);
+    g.com = reinterpret_cast<double*>(base + (size_t)kappa * N * sizeof(Mask));
+    for (int32_t t = 0; t < steps; ++t) {
+        hipLaunchKernelGGL(k_greedy_eval, dim3((unsigned)(kappa * N)), dim3(64), 0, s, g, (int)t);
+        hipLaunchKernelGGL(k_greedy_select, dim3(1), dim3(kSelThreads), 0, s, g, (int)t);
+    }
+    return hip_status(hipGetLastError());
+}
+
+}  // namespace thoi

@@ -55,11 +55,53 @@ def expand(solutions: np.ndarray, N: int) -> np.ndarray:
     return np.unique(rows, axis=0).astype(np.int32)
 
 
+def _to_masks(rows: np.ndarray, N: int) -> torch.Tensor:
+    """[n][k] index rows -> [n][2] int64 (two 64-bit mask words per row)."""
+    words = np.zeros((len(rows), 2), dtype=np.uint64)
+    for r, row in enumerate(rows):
+        for v in row:
+            words[r, int(v) // 64] |= np.uint64(1) << np.uint64(int(v) % 64)
+    return torch.from_numpy(words.view(np.int64).copy())
+
+
+def _from_masks(words: np.ndarray, N: int) -> np.ndarray:
+    i = np.arange(N)
+    bits = (words.view(np.uint64)[:, i // 64] >> (i % 64).astype(np.uint64)[None, :]) & np.uint64(1)
+    return np.array([np.nonzero(b)[0] for b in bits], dtype=np.int32)
+
+
+def _greedy_device(S: torch.Tensor, sols: np.ndarray, vals: np.ndarray, k_first: int, k_last: int, kappa: int,
+                   maximize: bool):
+    N = S.shape[0]
+    dev = S.device
+    steps = k_last - k_first
+    Sd = S.to(torch.float64).contiguous()
+    sm = torch.zeros((steps + 1, kappa, 2), dtype=torch.int64, device=dev)
+    sv = torch.zeros((steps + 1, kappa), dtype=torch.float64, device=dev)
+    cnt = torch.zeros(steps + 1, dtype=torch.int32, device=dev)
+    n0 = len(sols)
+    sm[0, :n0] = _to_masks(sols, N).to(dev)
+    sv[0, :n0] = torch.from_numpy(np.asarray(vals, dtype=np.float64)).to(dev)
+    cnt[0] = n0
+    ws = api._workspace(B.thoi_greedy_workspace_bytes(N, kappa), dev)
+    B.thoi_greedy(api._ptr(Sd), N, k_first, steps, kappa, 1 if maximize else 0, api._ptr(sm), api._ptr(sv),
+                  api._ptr(cnt), api._ptr(ws), ws.numel(), api._stream(dev))
+    sm, sv, cnt = sm.cpu().numpy(), sv.cpu().numpy(), cnt.cpu().numpy()
+    out = {}
+    for s in range(steps + 1):
+        n = int(cnt[s])
+        out[k_first + s] = (_from_masks(sm[s, :n], N).reshape(n, k_first + s), sv[s, :n])
+    return out
+
+
 def greedy(Sigma: torch.Tensor, k_first: int, k_last: int, kappa: int = 16, maximize: bool = True,
-           precision: str = "fp64"):
+           precision: str = "fp64", on_device: bool | None = None):
     """Greedy growth from order k_first to k_last.
 
     Returns {k: (solutions [<=kappa][k] int32, Omega [<=kappa])}, best first at every order.
+    on_device (default: with precision "fp64", N <= 128, k_last <= 64 and kappa * N <= 4096): the
+    orders after the first run on the device in one call (thoi_greedy: two launches per order, no
+    host round trip); otherwise every order is one batched reducer call decided on the host.
     """
     S = Sigma[0] if Sigma.dim() == 3 else Sigma
     N = S.shape[0]
@@ -82,6 +124,10 @@ def greedy(Sigma: torch.Tensor, k_first: int, k_last: int, kappa: int = 16, maxi
         rows = np.array(list(itertools.combinations(range(N), k_first)), dtype=np.int32).reshape(-1, k_first)
         sols, vals = _best_rows(S, rows, kappa, maximize, precision)
         out = {k_first: (sols, vals)}
+    if on_device is None:
+        on_device = precision == "fp64" and N <= 128 and k_last <= 64 and kappa * N <= 4096
+    if on_device and k_last > k_first and len(sols) > 0:
+        return _greedy_device(S, sols, out[k_first][1], k_first, k_last, kappa, maximize)
     for k in range(k_first + 1, k_last + 1):
         cand = expand(sols, N)
         sols, vals = _best_rows(S, cand, kappa, maximize, precision)

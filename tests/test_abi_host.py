@@ -248,6 +248,29 @@ def test_anneal_argument_errors(B):
     assert call(kappa=1 << 21) == B.THOI_EUNSUPPORTED
 
 
+def test_greedy_argument_errors(B):
+    """thoi_greedy rejects bad shapes and sizes before any launch."""
+    L = B.lib()
+    f = ctypes.c_void_p(0x1000)
+    need = B.thoi_greedy_workspace_bytes(100, 16)
+    assert need >= 100 * 16 * 24
+
+    def call(N=100, k0=3, steps=10, kappa=16, ws=need, out=f):
+        return L.thoi_greedy(f, N, k0, steps, kappa, 1, out, f, f, f, ws, None)
+    assert call(N=1) == B.THOI_EINVAL
+    assert call(N=129) == B.THOI_EINVAL
+    assert call(k0=0) == B.THOI_EINVAL
+    assert call(steps=-1) == B.THOI_EINVAL
+    assert call(kappa=0) == B.THOI_EINVAL
+    assert call(kappa=257) == B.THOI_EINVAL
+    assert call(N=20, k0=15, steps=6) == B.THOI_EINVAL          # beyond order N
+    assert call(k0=40, steps=25) == B.THOI_EUNSUPPORTED         # one wavefront factors orders up to 64
+    assert call(kappa=64) == B.THOI_EUNSUPPORTED                # 6400 candidates: above the selection's sort
+    assert call(out=None) == B.THOI_EINVAL
+    assert call(ws=16) == B.THOI_EWORKSPACE
+    assert call(steps=0, ws=0) == B.THOI_OK                     # nothing to do
+
+
 def test_launch_plan_stays_below_dispatch_limit(B):
     """Every engine grid stays below 2^30 work-items along x (the dispatch limit is 2^32), also for
     enumerations whose one-workgroup-per-n-plet wave grid would exceed it: FP64 orders 19..30 at
