@@ -19,13 +19,15 @@ namespace {
 
 constexpr int kMaxClasses = 8;
 
-// n-plets per lane of a class (consecutive, one unranking then successors): eight in the class
+// n-plets per lane of a class (consecutive, one unranking then successors): several in the class
 // of the smallest orders, whose factorisation is a few dozen instructions and where the
-// unranking would otherwise dominate; elsewhere as in the single-dataset engine.
+// unranking would otherwise dominate (FP32 six: at orders 3..5 over 1024 datasets four, six,
+// seven and eight per lane measured 1.89, 1.67, 2.0 and 2.11 ms); elsewhere as in the
+// single-dataset engine.
 template <typename F>
 __host__ __device__ constexpr int multi_per_lane(int khi)
 {
-    return khi <= (sizeof(F) == 4 ? 8 : 6) ? 8 : lane_per_thread<F>(khi, THOI_SEL_RANGE);
+    return khi <= (sizeof(F) == 4 ? 8 : 6) ? (sizeof(F) == 4 ? 6 : 8) : lane_per_thread<F>(khi, THOI_SEL_RANGE);
 }
 constexpr int kUpload = 512;          // datasets per upload launch
 constexpr int kPlanThreads = 1024;
