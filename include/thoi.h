@@ -326,21 +326,25 @@ thoi_status thoi_anneal(const double* Sigma, int32_t N, const uint64_t* masks0, 
  * Greedy growth run on the device (Methods, "Heuristics", "Greedy Algorithm").  Slot 0 holds the
  * starting solutions: count[0] <= kappa distinct n-plets of order k_first, as masks of the
  * N <= 128 variables (two 64-bit words each: variable i is bit i % 64 of word i / 64).  Step
- * s = 0 .. steps-1 extends every solution of slot s by every variable it lacks, evaluates Omega of
- * each distinct candidate of order k_first + s + 1 (FP64; a candidate that is not positive
- * definite is dropped) and writes the kappa best to slot s + 1, best first: the largest Omega
- * (maximize != 0) or the smallest, equal values ordered by the n-plet in lexicographic order
- * (the smaller first).
+ * s = 0 .. steps-1 extends every solution of slot s by every variable it lacks, evaluates each
+ * distinct candidate of order k_first + s + 1 in the D datasets (FP64) and writes the kappa best to
+ * slot s + 1, best first: the largest objective (maximize != 0) or the smallest, equal values
+ * ordered by the n-plet in lexicographic order (the smaller first).  The objective is the
+ * measure (0 TC, 1 DTC, 2 Omega, 3 S) combined over the datasets as thoi_objective does (`kind`:
+ * THOI_OBJ_MEAN, or THOI_OBJ_PAIRED_EFFECT with even D >= 4); a candidate whose objective is NaN
+ * (not positive definite in some dataset, or a zero spread) is dropped.  With D = 1 and
+ * THOI_OBJ_MEAN the objective is the measure itself.
+ *   Sigma: device [D][N][N] FP64.
  *   sols:  device [steps+1][kappa][2] uint64; vals: device [steps+1][kappa] FP64;
  *   count: device [steps+1] int32 (solutions in each slot); slot 0 (sols, vals, count) is input.
- *   ws:    device, >= thoi_greedy_workspace_bytes(N, kappa).
- * k_first + steps <= min(N, 64), kappa <= 256, kappa * N <= 4096.  Two kernel launches per step on
- * `stream`; nothing is allocated and the host does not wait.
+ *   ws:    device, >= thoi_greedy_workspace_bytes(D, N, kappa).
+ * k_first + steps <= min(N, 64), kappa <= 256, kappa * N <= 4096, D <= 65535.  Two kernel
+ * launches per step on `stream`; nothing is allocated and the host does not wait.
  */
-thoi_status thoi_greedy(const double* Sigma, int32_t N, int32_t k_first, int32_t steps, int32_t kappa,
-                        int32_t maximize, uint64_t* sols, double* vals, int32_t* count, void* ws, size_t ws_bytes,
-                        void* stream);
-size_t thoi_greedy_workspace_bytes(int32_t N, int32_t kappa);
+thoi_status thoi_greedy(const double* Sigma, int64_t D, int32_t N, int32_t k_first, int32_t steps, int32_t kappa,
+                        int32_t measure, int32_t kind, int32_t maximize, uint64_t* sols, double* vals, int32_t* count,
+                        void* ws, size_t ws_bytes, void* stream);
+size_t thoi_greedy_workspace_bytes(int64_t D, int32_t N, int32_t kappa);
 
 /* Initialise reducer arrays for D datasets (top_g = -1, hist = 0). */
 thoi_status thoi_reduce_init(const thoi_reduce* red, int64_t D, int32_t kmax, void* stream);

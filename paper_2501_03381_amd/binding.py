@@ -128,8 +128,8 @@ def lib():
     L.thoi_eval_launch_shape.argtypes = [I32, NP, OP, ctypes.POINTER(I32), ctypes.POINTER(I64)]
     D = ctypes.c_double
     L.thoi_anneal.argtypes = [P, I32, P, I32, I32, P, P, P, P, D, D, I32, I32, I32, I32, P, P, P, P, P, P]
-    L.thoi_greedy.argtypes = [P, I32, I32, I32, I32, I32, P, P, P, P, SZ, P]
-    L.thoi_greedy_workspace_bytes.argtypes = [I32, I32]
+    L.thoi_greedy.argtypes = [P, I64, I32, I32, I32, I32, I32, I32, I32, P, P, P, P, SZ, P]
+    L.thoi_greedy_workspace_bytes.argtypes = [I64, I32, I32]
     L.thoi_greedy_workspace_bytes.restype = SZ
     L.thoi_version.argtypes = []
     L.thoi_version.restype = ctypes.c_char_p
@@ -208,13 +208,14 @@ def thoi_anneal(Sigma, N, masks0, kappa, iters, move, a, b, accept, T0, alpha, m
                                            accepted, stream))
 
 
-def thoi_greedy(Sigma, N, k_first, steps, kappa, maximize, sols, vals, count, ws, ws_bytes, stream):
-    check("thoi_greedy", lib().thoi_greedy(Sigma, N, k_first, steps, kappa, maximize, sols, vals, count, ws, ws_bytes,
-                                           stream))
+def thoi_greedy(Sigma, D, N, k_first, steps, kappa, measure, kind, maximize, sols, vals, count, ws, ws_bytes,
+                stream):
+    check("thoi_greedy", lib().thoi_greedy(Sigma, D, N, k_first, steps, kappa, measure, kind, maximize, sols, vals,
+                                           count, ws, ws_bytes, stream))
 
 
-def thoi_greedy_workspace_bytes(N, kappa) -> int:
-    return int(lib().thoi_greedy_workspace_bytes(N, kappa))
+def thoi_greedy_workspace_bytes(D, N, kappa) -> int:
+    return int(lib().thoi_greedy_workspace_bytes(D, N, kappa))
 
 
 def thoi_objective_workspace_bytes(D, B, red=None) -> int:

@@ -375,22 +375,26 @@ thoi_status thoi_anneal(const double* Sigma, int32_t N, const uint64_t* masks0, 
                          (hipStream_t)stream);
 }
 
-thoi_status thoi_greedy(const double* Sigma, int32_t N, int32_t k_first, int32_t steps, int32_t kappa,
-                        int32_t maximize, uint64_t* sols, double* vals, int32_t* count, void* ws, size_t ws_bytes,
-                        void* stream)
+thoi_status thoi_greedy(const double* Sigma, int64_t D, int32_t N, int32_t k_first, int32_t steps, int32_t kappa,
+                        int32_t measure, int32_t kind, int32_t maximize, uint64_t* sols, double* vals, int32_t* count,
+                        void* ws, size_t ws_bytes, void* stream)
 {
-    if (N < 2 || N > 128 || k_first < 1 || steps < 0 || kappa < 1 || kappa > 256) return THOI_EINVAL;
+    if (D < 1 || N < 2 || N > 128 || k_first < 1 || steps < 0 || kappa < 1 || kappa > 256) return THOI_EINVAL;
+    if (measure < 0 || measure > 3) return THOI_EINVAL;
+    if (kind != THOI_OBJ_MEAN && kind != THOI_OBJ_PAIRED_EFFECT) return THOI_EINVAL;
+    if (kind == THOI_OBJ_PAIRED_EFFECT && (D % 2 != 0 || D < 4)) return THOI_EINVAL;
     if (k_first + steps > N) return THOI_EINVAL;
-    if (k_first + steps > 64 || (int64_t)kappa * N > greedy_select_max()) return THOI_EUNSUPPORTED;
+    if (D > 65535 || k_first + steps > 64 || (int64_t)kappa * N > greedy_select_max()) return THOI_EUNSUPPORTED;
     if (!Sigma || !sols || !vals || !count) return THOI_EINVAL;
     if (steps == 0) return THOI_OK;
-    if (!ws || ws_bytes < greedy_ws_bytes(N, kappa)) return THOI_EWORKSPACE;
-    return launch_greedy(Sigma, N, kappa, steps, maximize, sols, vals, count, ws, (hipStream_t)stream);
+    if (!ws || ws_bytes < greedy_ws_bytes(D, N, kappa)) return THOI_EWORKSPACE;
+    return launch_greedy(Sigma, D, N, kappa, steps, measure, kind, maximize, sols, vals, count, ws,
+                         (hipStream_t)stream);
 }
 
-size_t thoi_greedy_workspace_bytes(int32_t N, int32_t kappa)
+size_t thoi_greedy_workspace_bytes(int64_t D, int32_t N, int32_t kappa)
 {
-    return (N >= 1 && kappa >= 1) ? greedy_ws_bytes(N, kappa) : 0;
+    return (D >= 1 && N >= 1 && kappa >= 1) ? greedy_ws_bytes(D, N, kappa) : 0;
 }
 
 size_t thoi_objective_workspace_bytes(int64_t D, int64_t B, const thoi_reduce* red)

@@ -1,17 +1,20 @@
 // Greedy growth run on the device (Methods, "Heuristics", "Greedy Algorithm"): from the kappa
 // best n-plets of one order, every solution is extended by every variable it lacks, all
 // candidates of the next order are evaluated, and the kappa best are kept; the orders follow one
-// another with no host round trip (two launches per order).
+// another with no host round trip (two launches per order).  The objective is one measure (TC,
+// DTC, O-information or S-information) in one dataset, or its mean or paired effect size over D
+// datasets (Discussion: functions of the measures optimised across datasets).
 //
 // Candidate (p, v) is solution p extended by variable v.  A candidate reached from several parents
 // is evaluated once, from the first of them (the lowest p whose solution is a subset of it).  One
-// 64-lane workgroup per candidate factors its correlation block (FP64), taking the sums of the
-// logs in variable order, so candidates that differ only by which independent variable they hold
-// get bit-identical values.  One workgroup then sorts every candidate of the order by the
-// objective and, among equal values, by the n-plet in lexicographic order (the smaller first), and
-// keeps the first kappa.
+// 64-lane workgroup per candidate and dataset factors its correlation block (FP64), taking the
+// sums of the logs in variable order, so candidates that differ only by which independent
+// variable they hold get bit-identical values.  One workgroup then forms each candidate's
+// objective, sorts the candidates of the order by it and, among equal values, by the n-plet in
+// lexicographic order (the smaller first), and keeps the first kappa.
 #include "thoi_internal.hpp"
 #include "nplets_common.hpp"
+#include "objective_common.hpp"
 
 namespace thoi {
 namespace {
@@ -53,18 +56,22 @@ __device__ __forceinline__ uint64_t okey(double x)
 }
 
 struct GreedyArgs {
-    const double* Sigma;
+    const double* Sigma;    // [D][N][N]
+    int D;
     int N;
     int kappa;
-    double sign;            // +1: keep the largest Omega, -1: the smallest
+    int measure;            // 0 TC, 1 DTC, 2 Omega, 3 S
+    int kind;               // THOI_OBJ_MEAN or THOI_OBJ_PAIRED_EFFECT over the D datasets
+    double sign;            // +1: keep the largest objective, -1: the smallest
     Mask* sols;             // [steps + 1][kappa]; slot 0 holds the first order's solutions
     double* vals;           // [steps + 1][kappa]
     int32_t* count;         // [steps + 1]
     Mask* cmask;            // [kappa * N] candidates of the current step
-    double* com;            // [kappa * N] their Omega (NaN: not a candidate or not positive definite)
+    double* meas;           // [D][kappa * N] their measure (NaN: not a candidate or not positive definite)
 };
 
-// grid (kappa * N), block 64: candidate (p, v) = blockIdx.x / N, % N of step s (order k + 1).
+// grid (kappa * N, D), block 64: candidate (p, v) = blockIdx.x / N, % N of step s (order k + 1)
+// in dataset blockIdx.y.
 __global__ __launch_bounds__(64) void k_greedy_eval(GreedyArgs g, int s)
 {
     __shared__ double sM[64 * kGreedyKs];
@@ -73,7 +80,10 @@ __global__ __launch_bounds__(64) void k_greedy_eval(GreedyArgs g, int s)
     const int N = g.N;
     const int p = blockIdx.x / N, v = blockIdx.x % N;
     const int lane = threadIdx.x;
+    const int d = blockIdx.y;
     const int64_t slot = blockIdx.x;
+    double* meas = g.meas + (int64_t)d * g.kappa * N;
+    const double* Sig = g.Sigma + (int64_t)d * N * N;
     const int cnt = g.count[s];
     const Mask* sol = g.sols + (int64_t)s * g.kappa;
     // uniform in the workgroup: a parent that exists, a variable it lacks, and no earlier parent
@@ -87,7 +97,7 @@ __global__ __launch_bounds__(64) void k_greedy_eval(GreedyArgs g, int s)
         use = __all(use);                      // __all over the wavefront: every earlier parent checked
     }
     if (!use) {
-        if (lane == 0) g.com[slot] = __builtin_nan("");
+        if (lane == 0) meas[slot] = __builtin_nan("");
         return;
     }
     int k = popc(C);
@@ -109,12 +119,12 @@ __global__ __launch_bounds__(64) void k_greedy_eval(GreedyArgs g, int s)
             n -= c;
         }
         cidx[lane] = ci;
-        const double dj = g.Sigma[(int64_t)ci * N + ci];
+        const double dj = Sig[(int64_t)ci * N + ci];
         sIsd[lane] = dj > 0.0 ? 1.0 / sqrt(dj) : __builtin_nan("");
     }
     __syncthreads();
     if (lane < k) {
-        const double* row = g.Sigma + (int64_t)ci * N;
+        const double* row = Sig + (int64_t)ci * N;
         const double si = sIsd[lane];
         for (int j = 0; j < lane; ++j) sM[lane * kGreedyKs + j] = row[cidx[j]] * si * sIsd[j];
         sM[lane * kGreedyKs + lane] = 1.0;
@@ -124,13 +134,14 @@ __global__ __launch_bounds__(64) void k_greedy_eval(GreedyArgs g, int s)
     if (lane == 0) {
         const bool ok = f.ok && isfinite(f.ld) && isfinite(f.sa);
         const double TC = -0.5 * f.ld, DTC = 0.5 * (f.ld + f.sa);
-        g.cmask[slot] = C;
-        g.com[slot] = ok ? TC - DTC : __builtin_nan("");
+        const double m = g.measure == 0 ? TC : g.measure == 1 ? DTC : g.measure == 2 ? TC - DTC : TC + DTC;
+        if (d == 0) g.cmask[slot] = C;
+        meas[slot] = ok ? m : __builtin_nan("");
     }
 }
 
-// grid 1, block kSelThreads: sort the ncand = kappa * N slots of step s and keep the kappa best
-// distinct n-plets as step s + 1.
+// grid 1, block kSelThreads: the objective of each of the ncand = kappa * N slots of step s, then
+// sort them and keep the kappa best distinct n-plets as step s + 1.
 __global__ __launch_bounds__(kSelThreads) void k_greedy_select(GreedyArgs g, int s)
 {
     __shared__ uint64_t key[kSelMax];
@@ -139,7 +150,7 @@ __global__ __launch_bounds__(kSelThreads) void k_greedy_select(GreedyArgs g, int
     int P = 1;
     while (P < ncand) P <<= 1;
     for (int i = threadIdx.x; i < P; i += kSelThreads) {
-        const double o = i < ncand ? g.com[i] : __builtin_nan("");
+        const double o = i < ncand ? objective_of<double>(g.meas, g.D, ncand, i, g.kind) : __builtin_nan("");
         // ascending key = better first; invalid slots last
         key[i] = isnan(o) ? ~0ull : (g.sign > 0.0 ? ~okey(o) : okey(o));
         idx[i] = i < ncand ? i : -1;
@@ -167,7 +178,7 @@ __global__ __launch_bounds__(kSelThreads) void k_greedy_select(GreedyArgs g, int
         for (int i = 0; i < ncand && n < g.kappa; ++i) {
             if (key[i] == ~0ull) break;
             out[n] = g.cmask[idx[i]];
-            ov[n] = g.com[idx[i]];
+            ov[n] = objective_of<double>(g.meas, g.D, ncand, idx[i], g.kind);
             ++n;
         }
         g.count[s + 1] = n;
@@ -176,26 +187,33 @@ __global__ __launch_bounds__(kSelThreads) void k_greedy_select(GreedyArgs g, int
 
 }  // namespace
 
-size_t greedy_ws_bytes(int32_t N, int32_t kappa) { return (size_t)kappa * N * (sizeof(Mask) + 8) + 256; }
+size_t greedy_ws_bytes(int64_t D, int32_t N, int32_t kappa)
+{
+    return (size_t)kappa * N * (sizeof(Mask) + 8 * (size_t)D) + 256;
+}
 
 int greedy_select_max() { return kSelMax; }
 
-thoi_status launch_greedy(const double* Sigma, int32_t N, int32_t kappa, int32_t steps, int32_t maximize,
-                          uint64_t* sols, double* vals, int32_t* count, void* ws, hipStream_t s)
+thoi_status launch_greedy(const double* Sigma, int64_t D, int32_t N, int32_t kappa, int32_t steps, int32_t measure,
+                          int32_t kind, int32_t maximize, uint64_t* sols, double* vals, int32_t* count, void* ws,
+                          hipStream_t s)
 {
     GreedyArgs g{};
     g.Sigma = Sigma;
+    g.D = (int)D;
     g.N = N;
     g.kappa = kappa;
+    g.measure = measure;
+    g.kind = kind;
     g.sign = maximize ? 1.0 : -1.0;
     g.sols = reinterpret_cast<Mask*>(sols);
     g.vals = vals;
     g.count = count;
     char* base = static_cast<char*>(ws);
     g.cmask = reinterpret_cast<Mask*>(base);
-    g.com = reinterpret_cast<double*>(base + (size_t)kappa * N * sizeof(Mask));
+    g.meas = reinterpret_cast<double*>(base + (size_t)kappa * N * sizeof(Mask));
     for (int32_t t = 0; t < steps; ++t) {
-        hipLaunchKernelGGL(k_greedy_eval, dim3((unsigned)(kappa * N)), dim3(64), 0, s, g, (int)t);
+        hipLaunchKernelGGL(k_greedy_eval, dim3((unsigned)(kappa * N), (unsigned)D), dim3(64), 0, s, g, (int)t);
         hipLaunchKernelGGL(k_greedy_select, dim3(1), dim3(kSelThreads), 0, s, g, (int)t);
     }
     return hip_status(hipGetLastError());

@@ -4,34 +4,13 @@
 // datasets is what the paper's searches take as their objective (Discussion; Methods, "Greedy
 // Algorithm").
 #include "nplets_fwd_common.hpp"
+#include "objective_common.hpp"
 
 namespace thoi {
 namespace {
 
 constexpr int kObjTile = 256;
 constexpr int kObjMaxBlocks = 4096;
-
-template <typename VT>
-__device__ __forceinline__ double objective_of(const VT* __restrict__ v, int64_t D, int64_t B, int64_t b, int kind)
-{
-    if (kind == THOI_OBJ_MEAN) {
-        double s = 0.0;
-        for (int64_t d = 0; d < D; ++d) s += (double)v[d * B + b];
-        return s / (double)D;
-    }
-    // paired effect size: x_p = v[p] - v[P + p], mean / sd (P - 1 degrees of freedom)
-    const int64_t P = D / 2;
-    double s = 0.0;
-    for (int64_t p = 0; p < P; ++p) s += (double)v[p * B + b] - (double)v[(P + p) * B + b];
-    const double m = s / (double)P;
-    double q = 0.0;
-    for (int64_t p = 0; p < P; ++p) {
-        const double x = (double)v[p * B + b] - (double)v[(P + p) * B + b] - m;
-        q += x * x;
-    }
-    const double sd = sqrt(q / (double)(P - 1));
-    return sd > 0.0 ? m / sd : __builtin_nan("");
-}
 
 // grid (blocks), block kObjTile: tiles [blk * per_blk, (blk + 1) * per_blk) of n-plets.
 template <typename VT, bool RED>

@@ -71,11 +71,13 @@ def _from_masks(words: np.ndarray, N: int) -> np.ndarray:
 
 
 def _greedy_device(S: torch.Tensor, sols: np.ndarray, vals: np.ndarray, k_first: int, k_last: int, kappa: int,
-                   maximize: bool):
-    N = S.shape[0]
+                   maximize: bool, measure: int = 2, kind: int = B.THOI_OBJ_MEAN):
+    """Orders k_first+1..k_last on the device (thoi_greedy) from the first order's solutions.
+    S: [N, N] or [D, N, N]; the objective is `measure` combined over the D datasets by `kind`."""
+    Sd = (S[None] if S.dim() == 2 else S).to(torch.float64).contiguous()
+    D, N = Sd.shape[0], Sd.shape[1]
     dev = S.device
     steps = k_last - k_first
-    Sd = S.to(torch.float64).contiguous()
     sm = torch.zeros((steps + 1, kappa, 2), dtype=torch.int64, device=dev)
     sv = torch.zeros((steps + 1, kappa), dtype=torch.float64, device=dev)
     cnt = torch.zeros(steps + 1, dtype=torch.int32, device=dev)
@@ -83,9 +85,9 @@ def _greedy_device(S: torch.Tensor, sols: np.ndarray, vals: np.ndarray, k_first:
     sm[0, :n0] = _to_masks(sols, N).to(dev)
     sv[0, :n0] = torch.from_numpy(np.asarray(vals, dtype=np.float64)).to(dev)
     cnt[0] = n0
-    ws = api._workspace(B.thoi_greedy_workspace_bytes(N, kappa), dev)
-    B.thoi_greedy(api._ptr(Sd), N, k_first, steps, kappa, 1 if maximize else 0, api._ptr(sm), api._ptr(sv),
-                  api._ptr(cnt), api._ptr(ws), ws.numel(), api._stream(dev))
+    ws = api._workspace(B.thoi_greedy_workspace_bytes(D, N, kappa), dev)
+    B.thoi_greedy(api._ptr(Sd), D, N, k_first, steps, kappa, measure, kind, 1 if maximize else 0, api._ptr(sm),
+                  api._ptr(sv), api._ptr(cnt), api._ptr(ws), ws.numel(), api._stream(dev))
     sm, sv, cnt = sm.cpu().numpy(), sv.cpu().numpy(), cnt.cpu().numpy()
     out = {}
     for s in range(steps + 1):
@@ -367,16 +369,24 @@ def _best_rows_multi(Sigmas: torch.Tensor, rows: np.ndarray, kappa: int, measure
 
 
 def greedy_multi(Sigmas: torch.Tensor, k_first: int, k_last: int, kappa: int = 16, measure: str = "omega",
-                 kind: str = "mean", maximize: bool = True, precision: str = "fp64"):
+                 kind: str = "mean", maximize: bool = True, precision: str = "fp64", on_device: bool | None = None):
     """Greedy growth (as `greedy`) on an objective over D datasets: every candidate is evaluated in
     all D covariance matrices in one call (the paper's B x D pairing), `kind` ("mean" or
     "paired_effect") turns its D values of `measure` into one number on the device, and the kappa
-    best are kept by the reducer.  Sigmas: [D, N, N] float64.  Returns {k: (solutions, objective)}."""
+    best are kept.  Sigmas: [D, N, N] float64.  Returns {k: (solutions, objective)}.  on_device
+    (default: with precision "fp64", N <= 128, k_last <= 64 and kappa * N <= 4096): the orders
+    after the first run on the device in one call (thoi_greedy); otherwise each order is one
+    evaluator call plus one objective reduction, decided on the host."""
     import itertools
     D, N, _ = Sigmas.shape
     rows = np.array(list(itertools.combinations(range(N), k_first)), dtype=np.int32).reshape(-1, k_first)
     sols, vals = _best_rows_multi(Sigmas, rows, kappa, measure, kind, maximize, precision)
     out = {k_first: (sols, vals)}
+    if on_device is None:
+        on_device = precision == "fp64" and N <= 128 and k_last <= 64 and kappa * N <= 4096
+    if on_device and k_last > k_first and len(sols) > 0:
+        kd = B.THOI_OBJ_MEAN if kind == "mean" else B.THOI_OBJ_PAIRED_EFFECT
+        return _greedy_device(Sigmas, sols, vals, k_first, k_last, kappa, maximize, MEASURES[measure], kd)
     for k in range(k_first + 1, k_last + 1):
         sols, vals = _best_rows_multi(Sigmas, expand(sols, N), kappa, measure, kind, maximize, precision)
         out[k] = (sols, vals)

@@ -252,11 +252,18 @@ def test_greedy_argument_errors(B):
     """thoi_greedy rejects bad shapes and sizes before any launch."""
     L = B.lib()
     f = ctypes.c_void_p(0x1000)
-    need = B.thoi_greedy_workspace_bytes(100, 16)
+    need = B.thoi_greedy_workspace_bytes(1, 100, 16)
     assert need >= 100 * 16 * 24
+    assert B.thoi_greedy_workspace_bytes(8, 100, 16) >= 100 * 16 * (16 + 8 * 8)
 
-    def call(N=100, k0=3, steps=10, kappa=16, ws=need, out=f):
-        return L.thoi_greedy(f, N, k0, steps, kappa, 1, out, f, f, f, ws, None)
+    def call(N=100, k0=3, steps=10, kappa=16, ws=need, out=f, D=1, measure=2, kind=B.THOI_OBJ_MEAN):
+        return L.thoi_greedy(f, D, N, k0, steps, kappa, measure, kind, 1, out, f, f, f, ws, None)
+    assert call(D=0) == B.THOI_EINVAL
+    assert call(measure=4) == B.THOI_EINVAL
+    assert call(kind=7) == B.THOI_EINVAL
+    assert call(D=3, kind=B.THOI_OBJ_PAIRED_EFFECT) == B.THOI_EINVAL     # pairs need an even D >= 4
+    assert call(D=70000) == B.THOI_EUNSUPPORTED
+    assert call(D=4, ws=need) == B.THOI_EWORKSPACE                       # four datasets' measures
     assert call(N=1) == B.THOI_EINVAL
     assert call(N=129) == B.THOI_EINVAL
     assert call(k0=0) == B.THOI_EINVAL
