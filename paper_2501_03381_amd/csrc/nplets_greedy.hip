@@ -171,18 +171,16 @@ __global__ __launch_bounds__(kSelThreads) void k_greedy_select(GreedyArgs g, int
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        Mask* out = g.sols + (int64_t)(s + 1) * g.kappa;
-        double* ov = g.vals + (int64_t)(s + 1) * g.kappa;
-        int n = 0;
-        for (int i = 0; i < ncand && n < g.kappa; ++i) {
-            if (key[i] == ~0ull) break;
-            out[n] = g.cmask[idx[i]];
-            ov[n] = objective_of<double>(g.meas, g.D, ncand, idx[i], g.kind);
-            ++n;
-        }
-        g.count[s + 1] = n;
+    // the valid slots come first and are distinct n-plets: the first min(kappa, valid) are kept,
+    // one thread each
+    const int t = threadIdx.x;
+    const int n = __syncthreads_count(t < g.kappa && t < P && key[t] != ~0ull);
+    if (t < n) {
+        const int i = idx[t];
+        g.sols[(int64_t)(s + 1) * g.kappa + t] = g.cmask[i];
+        g.vals[(int64_t)(s + 1) * g.kappa + t] = objective_of<double>(g.meas, g.D, ncand, i, g.kind);
     }
+    if (t == 0) g.count[s + 1] = n;
 }
 
 }  // namespace
