@@ -3,13 +3,15 @@
 // evaluates its O-information (Eq. O-info with TC and DTC from one Cholesky factorisation) and
 // applies the Metropolis rule, so a whole run is enqueued without a host round trip.
 //
-// One 64-lane workgroup per chain: lane 0 forms the neighbour from the chain's mask and its
-// draws, the lanes gather the neighbour's correlation block straight from Sigma (L2-resident) and
-// the wavefront factors it (FP64, any order up to 64), and lane 0 takes the decision and updates
-// the chain's state.  Masks are two 64-bit words (N <= 128).  The random numbers are inputs (one
-// row of draws per iteration), so a run is reproducible bit for bit.
+// Orders up to 32: two chains per 64-lane wavefront, each half-wave factoring its chain's
+// neighbour with the rows in registers (the pair factorisation, entries read from Sigma in global
+// memory).  Larger orders (up to 64): one wavefront per chain, the block gathered into LDS.  In
+// both, the lane that owns a chain forms its neighbour from the chain's mask and draws, and takes
+// the decision and updates the chain's state.  Masks are two 64-bit words (N <= 128).  The random
+// numbers are inputs (one row of draws per iteration), so a run is reproducible bit for bit.
 #include "thoi_internal.hpp"
 #include "nplets_common.hpp"
+#include "pair_factor.hpp"
 
 namespace thoi {
 namespace {
@@ -87,6 +89,85 @@ __device__ __forceinline__ Mask propose(Mask cur, int N, bool across, int kmin, 
     return p;
 }
 
+// The chain's starting state, or one iteration's neighbour p, chosen for chain c.
+__device__ __forceinline__ Mask chain_neighbour(const AnnealArgs& g, bool init, const Mask* __restrict__ masks0,
+                                                int c, int64_t t)
+{
+    if (init) {
+        const Mask full = full_mask(g.N);
+        Mask p;
+        p.w[0] = masks0[c].w[0] & full.w[0];
+        p.w[1] = masks0[c].w[1] & full.w[1];
+        return p;
+    }
+    const int64_t e = t * g.kappa + c;
+    return propose(g.cur[c], g.N, g.across != 0, g.kmin, g.kmax, g.across ? g.move[e] : 0.0, g.a[e], g.b[e]);
+}
+
+// One thread per chain: the starting state (init), or the Metropolis decision on neighbour p.
+__device__ __forceinline__ void chain_update(const AnnealArgs& g, bool init, int c, int64_t t, double temp,
+                                             const Mask& p, const FactorOut<double>& f)
+{
+    // Omega = TC - DTC with TC = -ld/2 and DTC = (ld + sum_j log a_j)/2; NaN if not positive definite
+    const bool ok = f.ok && isfinite(f.ld) && isfinite(f.sa);
+    const double TC = -0.5 * f.ld, DTC = 0.5 * (f.ld + f.sa);
+    const double om = ok ? TC - DTC : __builtin_nan("");
+    if (init) {
+        g.cur[c] = p;
+        g.cur_om[c] = om;
+        g.best[c] = p;
+        g.best_om[c] = om;
+        g.acc[c] = 0;
+        return;
+    }
+    // energy E = sign * Omega; the neighbour is taken when dE > 0, else with probability
+    // exp(dE / temp); a neighbour that is not positive definite is never taken
+    const int64_t e = t * g.kappa + c;
+    const double E = g.sign * g.cur_om[c];
+    const double Ep = g.sign * om;
+    const double dE = Ep - E;
+    const bool take = ((dE > 0.0) || (g.u[e] < exp(dE / temp))) && !isnan(Ep);
+    Mask m = g.cur[c];
+    double mo = g.cur_om[c];
+    if (take) {
+        m = p;
+        mo = om;
+        g.cur[c] = p;
+        g.cur_om[c] = om;
+        g.acc[c] += 1;
+    }
+    if (g.sign * mo > g.sign * g.best_om[c]) {
+        g.best[c] = m;
+        g.best_om[c] = mo;
+    }
+}
+
+// grid (ceil(kappa / 2)), block 64: chain 2 blockIdx.x + h in half-wave h, orders up to kW2Max.
+template <bool INIT>
+__global__ __launch_bounds__(64) void k_anneal_pair(AnnealArgs g, const Mask* __restrict__ masks0, int64_t t,
+                                                    double temp)
+{
+    __shared__ double scol[2 * 2 * kW2Max], swrow[2 * 2 * kW2Max];
+    __shared__ int sch[2 * kW2Max];
+    __shared__ Mask sprop[2];
+    const int lane = threadIdx.x, h = lane >> 5, i = lane & 31;
+    const int c = 2 * blockIdx.x + h;
+    const bool live = c < g.kappa;
+    if (i == 0) sprop[h] = live ? chain_neighbour(g, INIT, masks0, c, t) : Mask{{0ull, 0ull}};
+    wave_sync();
+    const Mask p = sprop[h];
+    int kh = popc(p);
+    kh = kh < kW2Max ? kh : kW2Max;
+    int* ch = sch + h * kW2Max;
+    if (i < kh) ch[i] = nth_set(p, i);
+    wave_sync();
+    // every shuffle runs with the whole wavefront active
+    const int k0 = __shfl(kh, 0), k1 = __shfl(kh, 32);
+    const FactorOut<double> f = pair_factor<true>(g.Sigma, g.N, ch, k0 > k1 ? k0 : k1, kh, scol + h * 2 * kW2Max,
+                                                  swrow + h * 2 * kW2Max);
+    if (i == 0 && live) chain_update(g, INIT, c, t, temp, p, f);
+}
+
 // grid (kappa), block 64.  INIT: evaluate the starting masks; else iteration t at temperature temp.
 // LDS: sM [64 * kAnnealKs] | sInv [64] | sIsd [64] | cidx [64] | prop.
 template <bool INIT>
@@ -101,18 +182,7 @@ __global__ __launch_bounds__(64) void k_anneal(AnnealArgs g, const Mask* __restr
     const int c = blockIdx.x;
     const int lane = threadIdx.x;
 
-    if (lane == 0) {
-        Mask p;
-        if constexpr (INIT) {
-            const Mask full = full_mask(N);
-            p.w[0] = masks0[c].w[0] & full.w[0];
-            p.w[1] = masks0[c].w[1] & full.w[1];
-        } else {
-            const int64_t e = t * g.kappa + c;
-            p = propose(g.cur[c], N, g.across != 0, g.kmin, g.kmax, g.across ? g.move[e] : 0.0, g.a[e], g.b[e]);
-        }
-        sprop = p;
-    }
+    if (lane == 0) sprop = chain_neighbour(g, INIT, masks0, c, t);
     __syncthreads();
     const Mask p = sprop;
     int k = popc(p);
@@ -127,47 +197,10 @@ __global__ __launch_bounds__(64) void k_anneal(AnnealArgs g, const Mask* __restr
         sIsd[lane] = dj > 0.0 ? 1.0 / sqrt(dj) : __builtin_nan("");
     }
     __syncthreads();
-    if (lane < k) {
-        const double* row = g.Sigma + (int64_t)ci * N;
-        const double si = sIsd[lane];
-        for (int j = 0; j < lane; ++j) sM[lane * kAnnealKs + j] = row[cidx[j]] * si * sIsd[j];
-        sM[lane * kAnnealKs + lane] = 1.0;
-    }
+    if (lane < k) gather_row(g.Sigma + (int64_t)ci * N, cidx, sIsd, lane, sM + lane * kAnnealKs);
     __syncthreads();
     const FactorOut<double> f = wave_factor_core(k, sM, kAnnealKs, sInv);
-    if (lane != 0) return;
-    // Omega = TC - DTC with TC = -ld/2 and DTC = (ld + sum_j log a_j)/2; NaN if not positive definite
-    const bool ok = f.ok && isfinite(f.ld) && isfinite(f.sa);
-    const double TC = -0.5 * f.ld, DTC = 0.5 * (f.ld + f.sa);
-    const double om = ok ? TC - DTC : __builtin_nan("");
-    if constexpr (INIT) {
-        g.cur[c] = p;
-        g.cur_om[c] = om;
-        g.best[c] = p;
-        g.best_om[c] = om;
-        g.acc[c] = 0;
-    } else {
-        // energy E = sign * Omega; the neighbour is taken when dE > 0, else with probability
-        // exp(dE / temp); a neighbour that is not positive definite is never taken
-        const int64_t e = t * g.kappa + c;
-        const double E = g.sign * g.cur_om[c];
-        const double Ep = g.sign * om;
-        const double dE = Ep - E;
-        const bool take = ((dE > 0.0) || (g.u[e] < exp(dE / temp))) && !isnan(Ep);
-        Mask m = g.cur[c];
-        double mo = g.cur_om[c];
-        if (take) {
-            m = p;
-            mo = om;
-            g.cur[c] = p;
-            g.cur_om[c] = om;
-            g.acc[c] += 1;
-        }
-        if (g.sign * mo > g.sign * g.best_om[c]) {
-            g.best[c] = m;
-            g.best_om[c] = mo;
-        }
-    }
+    if (lane == 0) chain_update(g, INIT, c, t, temp, p, f);
 }
 
 }  // namespace
@@ -196,11 +229,16 @@ thoi_status launch_anneal(const double* Sigma, int32_t N, const uint64_t* masks0
     g.best_om = best_omega;
     g.acc = accepted;
     const Mask* m0 = reinterpret_cast<const Mask*>(masks0);
-    hipLaunchKernelGGL(k_anneal<true>, dim3((unsigned)kappa), dim3(64), 0, s, g, m0, (int64_t)0, 0.0);
+    // every order a chain can reach is at most k_max: the pair factorisation when it fits
+    const bool pair = k_max <= kW2Max;
+    const dim3 grid(pair ? (unsigned)((kappa + 1) / 2) : (unsigned)kappa);
+    if (pair) hipLaunchKernelGGL(k_anneal_pair<true>, grid, dim3(64), 0, s, g, m0, (int64_t)0, 0.0);
+    else hipLaunchKernelGGL(k_anneal<true>, grid, dim3(64), 0, s, g, m0, (int64_t)0, 0.0);
     // the temperature of iteration t is T0 multiplied by alpha t times, one product at a time
     double temp = T0;
     for (int32_t t = 0; t < iters; ++t) {
-        hipLaunchKernelGGL(k_anneal<false>, dim3((unsigned)kappa), dim3(64), 0, s, g, m0, (int64_t)t, temp);
+        if (pair) hipLaunchKernelGGL(k_anneal_pair<false>, grid, dim3(64), 0, s, g, m0, (int64_t)t, temp);
+        else hipLaunchKernelGGL(k_anneal<false>, grid, dim3(64), 0, s, g, m0, (int64_t)t, temp);
         temp *= alpha;
     }
     return hip_status(hipGetLastError());

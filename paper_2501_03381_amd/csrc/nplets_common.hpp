@@ -350,6 +350,24 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
+// Row `lane` of a correlation block gathered from the covariance row Sig[ci][.] (global memory):
+// out[j] = (Sigma_{ci, c_j} / sqrt(Sigma_ii)) / sqrt(Sigma_jj) for j < lane, out[lane] = 1, with
+// isd[j] = 1 / sqrt(Sigma_{c_j c_j}).  The loads go out eight at a time, all in flight together.
+__device__ __forceinline__ void gather_row(const double* __restrict__ row, const int* __restrict__ cidx,
+                                           const double* __restrict__ isd, int lane, double* __restrict__ out)
+{
+    const double si = isd[lane];
+    for (int j0 = 0; j0 < lane; j0 += 8) {
+        double e[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) e[u] = j0 + u < lane ? row[cidx[j0 + u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (j0 + u < lane) out[j0 + u] = e[u] * si * isd[j0 + u];
+    }
+    out[lane] = 1.0;
+}
+
 // Factorisation of the k x k block already gathered into the lower triangle of sM (row stride
 // ks, unit diagonal), one wavefront: log det, sum of log a_j and max a_j.  With sSeq (128
 // doubles of LDS) the two sums are taken by lane 0 in variable order instead of by a lane tree, so

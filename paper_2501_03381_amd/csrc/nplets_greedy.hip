@@ -123,12 +123,7 @@ __global__ __launch_bounds__(64) void k_greedy_eval(GreedyArgs g, int s)
         sIsd[lane] = dj > 0.0 ? 1.0 / sqrt(dj) : __builtin_nan("");
     }
     __syncthreads();
-    if (lane < k) {
-        const double* row = Sig + (int64_t)ci * N;
-        const double si = sIsd[lane];
-        for (int j = 0; j < lane; ++j) sM[lane * kGreedyKs + j] = row[cidx[j]] * si * sIsd[j];
-        sM[lane * kGreedyKs + lane] = 1.0;
-    }
+    if (lane < k) gather_row(Sig + (int64_t)ci * N, cidx, sIsd, lane, sM + lane * kGreedyKs);
     __syncthreads();
     const FactorOut<double> f = wave_factor_core(k, sM, kGreedyKs, sInv, sSeq);
     if (lane == 0) {

@@ -292,9 +292,11 @@ def anneal(Sigma: torch.Tensor, masks0: np.ndarray, draws: dict, T0: float = 1.0
         on_device = (precision == "fp64" and N <= 128 and ks.max() <= 64 and (mode == "within" or k_max <= 64)
                      and T0 > 0 and alpha > 0)
     if on_device:
-        # within an order the bounds only matter to the validation: clamp them to the kernel's range
-        kx = min(k_max, 64)
-        return _anneal_device(S, cur, draws, T0, alpha, maximize, mode, min(k_min, kx), kx)
+        # within an order no chain changes its order: the bounds are the initial orders (the
+        # device picks its factorisation by the largest order a chain can reach)
+        kx = int(ks.max()) if mode == "within" else k_max
+        kn = int(ks.min()) if mode == "within" else k_min
+        return _anneal_device(S, cur, draws, T0, alpha, maximize, mode, kn, kx)
     om = _omega_masks(S, cur, precision)
     E = sign * om
     best, Ebest = cur.copy(), E.copy()
