@@ -43,6 +43,22 @@ def _best_rows(Sigma: torch.Tensor, rows: np.ndarray, kappa: int, maximize: bool
     return rows[g[keep]], tv[0, k, slot][keep]
 
 
+def combinations(N: int, k: int) -> np.ndarray:
+    """Every k-subset of range(N) as sorted int32 rows [C(N, k)][k], in lexicographic order
+    (built level by level: each row is extended by every value above its last one)."""
+    rows = np.zeros((1, 0), dtype=np.int32)
+    for level in range(k):
+        last = rows[:, -1] if level > 0 else np.full(len(rows), -1, dtype=np.int64)
+        # values last+1 .. N-(k-level) keep room for the remaining levels
+        hi = N - (k - level)
+        cnt = np.maximum(hi - last, 0)
+        rep = np.repeat(np.arange(len(rows)), cnt)
+        start = np.repeat(np.cumsum(cnt) - cnt, cnt)
+        val = np.repeat(last + 1, cnt) + (np.arange(len(rep)) - start)
+        rows = np.concatenate([rows[rep], val[:, None].astype(np.int32)], axis=1)
+    return rows.astype(np.int32)
+
+
 def expand(solutions: np.ndarray, N: int) -> np.ndarray:
     """Every solution extended by each variable it lacks, sorted within rows, duplicates removed,
     rows in lexicographic order."""
@@ -122,8 +138,7 @@ def greedy(Sigma: torch.Tensor, k_first: int, k_last: int, kappa: int = 16, maxi
         out = {k_first: (sols, tv[0, k_first, slot][: len(g)])}
     else:
         # wider systems: the first order as an explicit list (lexicographic rows)
-        import itertools
-        rows = np.array(list(itertools.combinations(range(N), k_first)), dtype=np.int32).reshape(-1, k_first)
+        rows = combinations(N, k_first)
         sols, vals = _best_rows(S, rows, kappa, maximize, precision)
         out = {k_first: (sols, vals)}
     if on_device is None:
@@ -379,9 +394,8 @@ def greedy_multi(Sigmas: torch.Tensor, k_first: int, k_last: int, kappa: int = 1
     (default: with precision "fp64", N <= 128, k_last <= 64 and kappa * N <= 4096): the orders
     after the first run on the device in one call (thoi_greedy); otherwise each order is one
     evaluator call plus one objective reduction, decided on the host."""
-    import itertools
     D, N, _ = Sigmas.shape
-    rows = np.array(list(itertools.combinations(range(N), k_first)), dtype=np.int32).reshape(-1, k_first)
+    rows = combinations(N, k_first)
     sols, vals = _best_rows_multi(Sigmas, rows, kappa, measure, kind, maximize, precision)
     out = {k_first: (sols, vals)}
     if on_device is None:

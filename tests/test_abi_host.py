@@ -331,3 +331,14 @@ def test_tuner_keys_and_cache_lookup(tmp_path, monkeypatch):
     assert tune.lookup_range("gfx942", "fp32_refine", 20, 1) is None     # another architecture
     assert tune.lookup_multi("gfx950", "fp32", [12, 33, 40], 3, 5) == (4, 512)
     assert tune.lookup_multi("gfx950", "fp32", [12, 33, 40], 3, 6) is None
+
+
+def test_search_combinations_match_itertools():
+    """The greedy's first-order rows: every k-subset in lexicographic order, as itertools gives."""
+    import itertools
+    from paper_2501_03381_amd.search import combinations
+    for N, k in ((100, 3), (20, 1), (20, 5), (7, 7), (5, 0), (30, 4), (1, 1), (64, 2), (6, 3)):
+        ref = list(itertools.combinations(range(N), k))
+        got = combinations(N, k)
+        assert got.dtype == np.int32 and got.shape == (len(ref), k), (N, k)
+        assert [tuple(int(x) for x in r) for r in got] == ref, (N, k)
