@@ -388,7 +388,7 @@ thoi_status thoi_greedy(const double* Sigma, int64_t D, int32_t N, int32_t k_fir
     if (!Sigma || !sols || !vals || !count) return THOI_EINVAL;
     if (steps == 0) return THOI_OK;
     if (!ws || ws_bytes < greedy_ws_bytes(D, N, kappa)) return THOI_EWORKSPACE;
-    return launch_greedy(Sigma, D, N, kappa, steps, measure, kind, maximize, sols, vals, count, ws,
+    return launch_greedy(Sigma, D, N, k_first, kappa, steps, measure, kind, maximize, sols, vals, count, ws,
                          (hipStream_t)stream);
 }
 

@@ -15,6 +15,7 @@
 #include "thoi_internal.hpp"
 #include "nplets_common.hpp"
 #include "objective_common.hpp"
+#include "pair_factor.hpp"
 
 namespace thoi {
 namespace {
@@ -135,6 +136,71 @@ __global__ __launch_bounds__(64) void k_greedy_eval(GreedyArgs g, int s)
     }
 }
 
+// grid (ceil(kappa * N / 2), D), block 64: two candidate slots per wavefront (half-wave h takes
+// slot 2 blockIdx.x + h), factored with the rows in registers; for steps whose order is at most
+// kW2Max.  The same candidates, measures and sums in variable order as k_greedy_eval.
+__global__ __launch_bounds__(64) void k_greedy_eval_pair(GreedyArgs g, int s)
+{
+    __shared__ double scol[2 * 2 * kW2Max], swrow[2 * 2 * kW2Max];
+    __shared__ int sch[2 * kW2Max];
+    const int N = g.N;
+    const int lane = threadIdx.x, h = lane >> 5, i = lane & 31;
+    const int64_t slot = 2 * (int64_t)blockIdx.x + h;
+    const int64_t nslot = (int64_t)g.kappa * N;
+    const int d = blockIdx.y;
+    double* meas = g.meas + (int64_t)d * nslot;
+    const double* Sig = g.Sigma + (int64_t)d * N * N;
+    const int cnt = g.count[s];
+    const Mask* sol = g.sols + (int64_t)s * g.kappa;
+    const int p = slot < nslot ? (int)(slot / N) : 0, v = slot < nslot ? (int)(slot % N) : 0;
+    // uniform in the half-wave: a slot that exists, a parent that exists, a variable it lacks, and
+    // no earlier parent reaching the same n-plet
+    bool use = slot < nslot && p < cnt && !has(sol[p], v);
+    Mask C{};
+    if (use) {
+        C = sol[p];
+        C.w[v >> 6] |= 1ull << (v & 63);
+    }
+    bool lane_ok = true;
+    if (use)
+        for (int q = i; q < p; q += 32) lane_ok = lane_ok && !subset(sol[q], C);
+    const uint64_t bad = __ballot(!lane_ok);               // whole wavefront active
+    use = use && ((bad >> (32 * h)) & 0xffffffffull) == 0;
+    int kh = use ? popc(C) : 0;
+    kh = kh < kW2Max ? kh : kW2Max;
+    int* ch = sch + h * kW2Max;
+    if (i < kh) {
+        Mask m = C;
+        int n = i, ci = 0;
+        for (int hw = 0; hw < 2; ++hw) {
+            const int c = __popcll(m.w[hw]);
+            if (n < c) {
+                uint64_t x = m.w[hw];
+                for (int t = 0; t < n; ++t) x &= x - 1;
+                ci = 64 * hw + __builtin_ctzll(x);
+                break;
+            }
+            n -= c;
+        }
+        ch[i] = ci;
+    }
+    wave_sync();
+    const int k0 = __shfl(kh, 0), k1 = __shfl(kh, 32);
+    const FactorOut<double> f = pair_factor<true, true>(Sig, N, ch, k0 > k1 ? k0 : k1, kh, scol + h * 2 * kW2Max,
+                                                        swrow + h * 2 * kW2Max);
+    if (i == 0 && slot < nslot) {
+        if (!use) {
+            meas[slot] = __builtin_nan("");
+        } else {
+            const bool ok = f.ok && isfinite(f.ld) && isfinite(f.sa);
+            const double TC = -0.5 * f.ld, DTC = 0.5 * (f.ld + f.sa);
+            const double m = g.measure == 0 ? TC : g.measure == 1 ? DTC : g.measure == 2 ? TC - DTC : TC + DTC;
+            if (d == 0) g.cmask[slot] = C;
+            meas[slot] = ok ? m : __builtin_nan("");
+        }
+    }
+}
+
 // grid 1, block kSelThreads: the objective of each of the ncand = kappa * N slots of step s, then
 // sort them and keep the kappa best distinct n-plets as step s + 1.
 __global__ __launch_bounds__(kSelThreads) void k_greedy_select(GreedyArgs g, int s)
@@ -192,9 +258,9 @@ size_t greedy_ws_bytes(int64_t D, int32_t N, int32_t kappa)
 
 int greedy_select_max() { return kSelMax; }
 
-thoi_status launch_greedy(const double* Sigma, int64_t D, int32_t N, int32_t kappa, int32_t steps, int32_t measure,
-                          int32_t kind, int32_t maximize, uint64_t* sols, double* vals, int32_t* count, void* ws,
-                          hipStream_t s)
+thoi_status launch_greedy(const double* Sigma, int64_t D, int32_t N, int32_t k_first, int32_t kappa, int32_t steps,
+                          int32_t measure, int32_t kind, int32_t maximize, uint64_t* sols, double* vals, int32_t* count,
+                          void* ws, hipStream_t s)
 {
     GreedyArgs g{};
     g.Sigma = Sigma;
@@ -211,7 +277,12 @@ thoi_status launch_greedy(const double* Sigma, int64_t D, int32_t N, int32_t kap
     g.cmask = reinterpret_cast<Mask*>(base);
     g.meas = reinterpret_cast<double*>(base + (size_t)kappa * N * sizeof(Mask));
     for (int32_t t = 0; t < steps; ++t) {
-        hipLaunchKernelGGL(k_greedy_eval, dim3((unsigned)(kappa * N), (unsigned)D), dim3(64), 0, s, g, (int)t);
+        // step t builds order k_first + t + 1
+        if (k_first + t + 1 <= kW2Max)
+            hipLaunchKernelGGL(k_greedy_eval_pair, dim3((unsigned)((kappa * N + 1) / 2), (unsigned)D), dim3(64), 0, s, g,
+                               (int)t);
+        else
+            hipLaunchKernelGGL(k_greedy_eval, dim3((unsigned)(kappa * N), (unsigned)D), dim3(64), 0, s, g, (int)t);
         hipLaunchKernelGGL(k_greedy_select, dim3(1), dim3(kSelThreads), 0, s, g, (int)t);
     }
     return hip_status(hipGetLastError());

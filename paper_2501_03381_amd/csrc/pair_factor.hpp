@@ -37,8 +37,10 @@ __device__ __forceinline__ double half_max(double v)
 // wavefront pass the same k (>= the kh of each): the loops run to k.  GLOBAL: entries from the
 // covariance Sig in global memory, scaled by 1/sqrt(Sigma_ii Sigma_jj) (each half may have its
 // own dataset); otherwise from the staged correlation matrix sR.  col and wrow: two buffers of 32
-// doubles each, per half.  Returns the FactorOut in every lane.
-template <bool GLOBAL>
+// doubles each, per half.  Returns the FactorOut in every lane.  SEQ: the two log sums are taken
+// by the half's lane 0 in row order instead of by a lane tree, so inserting an independent
+// variable (a zero row and column) changes no bit of them.
+template <bool GLOBAL, bool SEQ = false>
 __device__ __forceinline__ FactorOut<double> pair_factor(const double* __restrict__ sR, int N,
                                                          const int* __restrict__ cidx, int k_in, int kh,
                                                          double* __restrict__ col, double* __restrict__ wrow)
@@ -134,8 +136,21 @@ __device__ __forceinline__ FactorOut<double> pair_factor(const double* __restric
         }
     });
     FactorOut<double> o;
-    o.ld = half_sum(mine ? log(piv) : 0.0);
-    o.sa = half_sum(mine ? log(aj) : 0.0);
+    if constexpr (SEQ) {
+        wave_sync();                                      // every lane has read its last W row
+        wrow[i] = mine ? log(piv) : 0.0;
+        wrow[kW2Max + i] = mine ? log(aj) : 0.0;
+        wave_sync();
+        double s1 = 0.0, s2 = 0.0;
+        if (i == 0) {
+            for (int m = 0; m < kh; ++m) { s1 += wrow[m]; s2 += wrow[kW2Max + m]; }
+        }
+        o.ld = __shfl(s1, 0, 32);
+        o.sa = __shfl(s2, 0, 32);
+    } else {
+        o.ld = half_sum(mine ? log(piv) : 0.0);
+        o.sa = half_sum(mine ? log(aj) : 0.0);
+    }
     o.vmax = half_max(mine ? aj : 0.0);
     o.ok = half_sum((mine && !(piv > 0.0)) ? 1.0 : 0.0) == 0.0;
     wave_sync();

@@ -95,9 +95,9 @@ thoi_status launch_objective(const void* vals, int32_t val_dtype, int64_t D, int
 size_t objective_ws_bytes(int64_t D, int64_t B, const thoi_reduce* red);
 size_t greedy_ws_bytes(int64_t D, int32_t N, int32_t kappa);
 int greedy_select_max();
-thoi_status launch_greedy(const double* Sigma, int64_t D, int32_t N, int32_t kappa, int32_t steps, int32_t measure,
-                          int32_t kind, int32_t maximize, uint64_t* sols, double* vals, int32_t* count, void* ws,
-                          hipStream_t s);
+thoi_status launch_greedy(const double* Sigma, int64_t D, int32_t N, int32_t k_first, int32_t kappa, int32_t steps,
+                          int32_t measure, int32_t kind, int32_t maximize, uint64_t* sols, double* vals, int32_t* count,
+                          void* ws, hipStream_t s);
 thoi_status launch_anneal(const double* Sigma, int32_t N, const uint64_t* masks0, int32_t kappa, int32_t iters,
                           const double* draw_move, const double* draw_a, const double* draw_b, const double* draw_u,
                           double T0, double alpha, int32_t maximize, int32_t across, int32_t k_min, int32_t k_max,
