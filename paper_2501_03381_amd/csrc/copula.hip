@@ -250,16 +250,14 @@ __global__ __launch_bounds__(kMergeThreads) void k_copula_merge(int64_t T, int64
             const bool le = o0 + s < q;           // equal values of an earlier chunk come first
 #pragma unroll
             for (int e = 0; e < kMergeReg; ++e) {
-                const uint64_t x = mk[e];
-                // count of entries before x: binary digits from the top, then the last entry
+                // count of entries before x (v < x, or v <= x for an earlier chunk: v < x + 1; a
+                // real key is below ~0, and the padding slots' ranks are never stored): binary
+                // digits from the top, then the last entry
+                const uint64_t xs = le ? mk[e] + 1 : mk[e];
                 int pos = 0;
 #pragma unroll
-                for (int b = kChunk / 2; b >= 1; b >>= 1) {
-                    const uint64_t v = okey[s][pos + b - 1];
-                    pos += (v < x || (le && v == x)) ? b : 0;
-                }
-                const uint64_t v = okey[s][pos];
-                pos += (v < x || (le && v == x)) ? 1 : 0;
+                for (int b = kChunk / 2; b >= 1; b >>= 1) pos += okey[s][pos + b - 1] < xs ? b : 0;
+                pos += okey[s][pos] < xs ? 1 : 0;
                 rank[e] += pos;
             }
         }
