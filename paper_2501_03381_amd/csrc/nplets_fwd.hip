@@ -223,11 +223,16 @@ int pfx_class_of(bool f64, int k)
 }
 
 // Whether a whole order k of a RANGE call goes to the prefix engine.  The library's choice
-// (THOI_ENGINE_AUTO) follows measurements of both engines on the N = 30 reduction, orders 7..12 in
-// one call: in FP64 the prefix engine took 22.4 ms against 30.2 ms; in FP32 13.0 ms against
-// 11.9 ms (the factorisation engine's concurrent class launches keep the GPU fuller).  Orders up
-// to 6 have too few prefixes per workgroup, and in output mode each lane's outputs are consecutive
-// but the lanes' are far apart, so the stores do not coalesce.
+// (THOI_ENGINE_AUTO) follows measurements of both engines on the N = 30 reduction (streaming
+// top-100 and 256 bins): orders 7..8 FP64 1.31 ms against 1.55 ms, FP32 + refinement 1.28 against
+// 1.49; orders 9..12 FP64 9.4 against 14.4 ms, FP32 + refinement 5.6 against 6.9; orders 13..16
+// FP32 + refinement 33.5 against 28.6 ms (the factorisation engine wins).  In FP32 the gain on
+// orders 7..12 alone does not carry over to a whole enumeration, where the factorisation classes
+// of those orders overlap the longer ones (all orders 3..30: 67.7 ms with the prefix engine for
+// 7..12, 67.2 ms without), so FP32 keeps the factorisation engine.  Orders up to 6 have too few
+// prefixes per workgroup (3..6: 1.4 against 0.8 ms), at N = 20 every order has too few tails per
+// prefix, and in output mode each lane's outputs are consecutive but the lanes' are far apart, so
+// the stores do not coalesce.
 bool use_prefix(int engine, bool reduce, bool f64, int N, int k, int64_t D)
 {
     if (engine == THOI_ENGINE_PREFIX) return true;
