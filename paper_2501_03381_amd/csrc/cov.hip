@@ -19,6 +19,7 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 constexpr int kCovThreads = 256;   // four waves
 constexpr int kSlab = 128;         // samples per workgroup
 constexpr int kStageLd = kSlab * 32 / kCovThreads;   // staged values per thread
+constexpr int kFinReg = 4;          // slabs per lane held in registers by the finish (T <= 32768)
 
 template <typename ZT>
 __device__ __forceinline__ double ld_z(const void* Z, int64_t off) { return (double)static_cast<const ZT*>(Z)[off]; }
@@ -121,16 +122,43 @@ __global__ __launch_bounds__(256) void k_cov_finish(const double* __restrict__ p
     const int64_t b = a + e;
     const double* ms = smean + (int64_t)d * nslabs * N;
     auto cnt = [&](int sl) { return (double)(min<int64_t>(T, (int64_t)(sl + 1) * kSlab) - (int64_t)sl * kSlab); };
-    double ma = 0.0, mb = 0.0;
-    for (int sl = lane; sl < nslabs; sl += 64) {
-        ma += cnt(sl) * ms[sl * N + a];
-        mb += cnt(sl) * ms[sl * N + b];
+    double ma = 0.0, mb = 0.0, s = 0.0;
+    if (nslabs <= 64 * kFinReg) {
+        // every load of the lane in flight together; the sums run in the same order as below
+        double pa[kFinReg], pb[kFinReg], pp[kFinReg];
+#pragma unroll
+        for (int r = 0; r < kFinReg; ++r) {
+            const int sl = lane + 64 * r;
+            const bool in = sl < nslabs;
+            pa[r] = in ? ms[sl * N + a] : 0.0;
+            pb[r] = in ? ms[sl * N + b] : 0.0;
+            pp[r] = in ? partial[((d * nslabs + sl) * Np + a) * Np + b] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < kFinReg; ++r) {
+            const int sl = lane + 64 * r;
+            if (sl < nslabs) {
+                ma += cnt(sl) * pa[r];
+                mb += cnt(sl) * pb[r];
+            }
+        }
+        ma = wave_sum_fixed(ma) / (double)T;
+        mb = wave_sum_fixed(mb) / (double)T;
+#pragma unroll
+        for (int r = 0; r < kFinReg; ++r) {
+            const int sl = lane + 64 * r;
+            if (sl < nslabs) s += pp[r] + cnt(sl) * (pa[r] - ma) * (pb[r] - mb);
+        }
+    } else {
+        for (int sl = lane; sl < nslabs; sl += 64) {
+            ma += cnt(sl) * ms[sl * N + a];
+            mb += cnt(sl) * ms[sl * N + b];
+        }
+        ma = wave_sum_fixed(ma) / (double)T;
+        mb = wave_sum_fixed(mb) / (double)T;
+        for (int sl = lane; sl < nslabs; sl += 64)
+            s += partial[((d * nslabs + sl) * Np + a) * Np + b] + cnt(sl) * (ms[sl * N + a] - ma) * (ms[sl * N + b] - mb);
     }
-    ma = wave_sum_fixed(ma) / (double)T;
-    mb = wave_sum_fixed(mb) / (double)T;
-    double s = 0.0;
-    for (int sl = lane; sl < nslabs; sl += 64)
-        s += partial[((d * nslabs + sl) * Np + a) * Np + b] + cnt(sl) * (ms[sl * N + a] - ma) * (ms[sl * N + b] - mb);
     s = wave_sum_fixed(s) / (double)(T - 1);
     if (lane == 0) {
         Sigma[(d * N + a) * N + b] = s;
