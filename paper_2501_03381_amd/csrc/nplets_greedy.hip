@@ -207,7 +207,7 @@ __global__ __launch_bounds__(kSelThreads) void k_greedy_select(GreedyArgs g, int
 {
     __shared__ uint64_t key[kSelMax];
     __shared__ int idx[kSelMax];
-    __shared__ Mask msk[kSelMax];           // the n-plets ride along for the lexicographic ties
+    __shared__ Mask msk[kSelMax];           // the n-plets by slot, read for the lexicographic ties
     const int ncand = g.kappa * g.N;
     int P = 1;
     while (P < ncand) P <<= 1;
@@ -226,13 +226,10 @@ __global__ __launch_bounds__(kSelThreads) void k_greedy_select(GreedyArgs g, int
                 const bool asc = (lo & size) == 0;
                 const uint64_t ka = key[lo], kb = key[hi];
                 const int ia = idx[lo], ib = idx[hi];
-                const Mask ma = msk[lo], mb = msk[hi];
                 // b before a: smaller key, or equal valid keys and the lexicographically smaller n-plet
                 bool b_first = kb < ka;
-                if (kb == ka && ka != ~0ull) b_first = lex_less(mb, ma);
-                if (b_first == asc) {
-                    key[lo] = kb; key[hi] = ka; idx[lo] = ib; idx[hi] = ia; msk[lo] = mb; msk[hi] = ma;
-                }
+                if (kb == ka && ka != ~0ull) b_first = lex_less(msk[ib], msk[ia]);
+                if (b_first == asc) { key[lo] = kb; key[hi] = ka; idx[lo] = ib; idx[hi] = ia; }
             }
         }
     }
@@ -243,7 +240,7 @@ __global__ __launch_bounds__(kSelThreads) void k_greedy_select(GreedyArgs g, int
     const int n = __syncthreads_count(t < g.kappa && t < P && key[t] != ~0ull);
     if (t < n) {
         const int i = idx[t];
-        g.sols[(int64_t)(s + 1) * g.kappa + t] = msk[t];
+        g.sols[(int64_t)(s + 1) * g.kappa + t] = msk[i];
         g.vals[(int64_t)(s + 1) * g.kappa + t] = objective_of<double>(g.meas, g.D, ncand, i, g.kind);
     }
     if (t == 0) g.count[s + 1] = n;
