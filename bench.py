@@ -384,6 +384,8 @@ def bench_greedy(torch, np, api, B, synth, dev, args):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         evaluated = math.comb(100, 3) + sum(len(search.expand(out[k - 1][0], 100)) for k in range(4, 41))
+        search.swap_refine(Sd, out[20][0][:1], maximize=maximize, top_m=4, max_iter=1)      # warm-up
+        torch.cuda.synchronize()
         t1 = time.perf_counter()
         sols, vals, its = search.swap_refine(Sd, out[20][0][:4], maximize=maximize, top_m=64)
         torch.cuda.synchronize()
