@@ -15,6 +15,7 @@
 #include "nplets_fwd_common.hpp"
 
 namespace thoi {
+static_assert(kTile <= 64 * kRedWaves, "the reducer keeps lists for at most kRedWaves wavefronts");
 namespace {
 
 constexpr int kMaxClasses = 8;

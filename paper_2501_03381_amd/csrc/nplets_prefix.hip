@@ -27,6 +27,7 @@
 #include "nplets_prefix.hpp"
 
 namespace thoi {
+static_assert(kPfxThreads <= 64 * kRedWaves, "the reducer keeps lists for at most kRedWaves wavefronts");
 namespace {
 
 // Tail depth for order K: the variables appended to a shared prefix of K - S variables.

@@ -17,6 +17,7 @@
 #include "pair_factor.hpp"
 
 namespace thoi {
+static_assert(kPairThreads <= 64 * kRedWaves, "the reducer keeps lists for at most kRedWaves wavefronts");
 namespace {
 
 // Lexicographic unranking of rank r among the k-subsets of {0..N-1} (one lane), binomials from the

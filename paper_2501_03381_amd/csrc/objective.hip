@@ -11,6 +11,7 @@ namespace {
 
 constexpr int kObjTile = 256;
 constexpr int kObjMaxBlocks = 4096;
+static_assert(kObjTile <= 64 * kRedWaves, "the reducer keeps lists for at most kRedWaves wavefronts");
 
 // grid (blocks), block kObjTile: tiles [blk * per_blk, (blk + 1) * per_blk) of n-plets.
 template <typename VT, bool RED>
