@@ -72,6 +72,9 @@ def test_copulize_one_and_many_chunks(env):
                     ("T=20000 N=3", np.random.default_rng(1).standard_normal((20000, 3))),
                     ("T=1024 N=5", np.random.default_rng(4).standard_normal((1024, 5))),
                     ("T=1025 N=5", np.random.default_rng(5).standard_normal((1025, 5))),
+                    ("T=2048 N=4", np.random.default_rng(6).standard_normal((2048, 4))),
+                    ("T=2049 N=4", np.random.default_rng(7).standard_normal((2049, 4))),
+                    ("T=4097 N=3 with ties", np.round(np.random.default_rng(8).standard_normal((4097, 3)), 1)),
                     ("T=2 N=2", np.array([[1.0, 3.0], [0.5, 3.0]]))):
         say(f"copulize {name}")
         Z = host(api.copulize(dev(torch, X)))
