@@ -187,6 +187,28 @@ def test_anneal_device_matches_host_loop_wide(env):
             assert got[4].sum() > 0
 
 
+def test_search_device_loops_above_order_32(env):
+    """Orders above 32 take the one-wavefront-per-n-plet kernels of the device greedy and
+    annealer: both equal the host-driven loops on the 100-variable latent model."""
+    torch, search, osearch, synth, orc = env
+    S = orc.gc_covariance(synth.latent_100()[0])
+    say("greedy N=100 orders 3..36 kappa 4: device vs host loop")
+    got = search.greedy(dev(torch, S), 3, 36, kappa=4, maximize=False, on_device=True)
+    ref = search.greedy(dev(torch, S), 3, 36, kappa=4, maximize=False, on_device=False)
+    for k in range(3, 37):
+        assert np.array_equal(got[k][0], ref[k][0]), k
+        assert np.abs(got[k][1] - ref[k][1]).max() < 1e-9, k
+    m0 = synth.sa_initial(51, 12, 100, 33, 38)
+    dr = synth.sa_draws(52, 12, 12)
+    say("anneal N=100 kappa 12 x 12 across orders 30..40: device vs host loop")
+    kw = dict(T0=0.2, alpha=0.97, maximize=True, mode="across", k_min=30, k_max=40)
+    got = search.anneal(dev(torch, S), m0, dr, on_device=True, **kw)
+    ref = search.anneal(dev(torch, S), m0, dr, on_device=False, **kw)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[2], ref[2])
+    assert np.array_equal(got[4], ref[4])
+    assert np.abs(got[1] - ref[1]).max() < 1e-9 and np.abs(got[3] - ref[3]).max() < 1e-9
+
+
 def test_anneal_pgm_blocks(env):
     torch, search, osearch, synth, orc = env
     S = synth.block_diag(synth.r_system(5, 1.0), synth.s_system(5, 1.0), np.eye(6))
