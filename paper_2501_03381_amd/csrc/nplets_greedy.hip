@@ -218,9 +218,16 @@ __global__ __launch_bounds__(kSelThreads) void k_greedy_select(GreedyArgs g, int
         idx[i] = i < ncand ? i : -1;
         msk[i] = isnan(o) ? Mask{{0ull, 0ull}} : g.cmask[i];
     }
+    // Thread 1024 j + 64 w + r of a stage with stride <= 64 exchanges elements of the 128-entry
+    // chunk 2048 j + 128 w only, so between two such stages wavefront w waits for itself alone; a
+    // stage that follows or precedes one with a wider stride (or the fill above) waits for the block.
+    bool wide = true;
     for (int size = 2; size <= P; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            __syncthreads();
+            const bool w = stride > 64;
+            if (w || wide) __syncthreads();
+            else wave_sync();
+            wide = w;
             for (int i = threadIdx.x; i < (P >> 1); i += kSelThreads) {
                 const int lo = 2 * i - (i & (stride - 1)), hi = lo + stride;
                 const bool asc = (lo & size) == 0;
