@@ -201,8 +201,28 @@ __global__ __launch_bounds__(64) void k_greedy_eval_pair(GreedyArgs g, int s)
     }
 }
 
+constexpr int kSelChunk = 128;         // entries one wavefront sorts on its own (two per lane)
+
+// Entry (kx, ix) goes before entry (ky, iy): the smaller key, or equal valid keys and the
+// lexicographically smaller n-plet (valid slots hold distinct n-plets, so the order is strict there).
+__device__ __forceinline__ bool sel_before(uint64_t kx, int ix, uint64_t ky, int iy, const Mask* msk)
+{
+    if (kx != ky) return kx < ky;
+    return ky != ~0ull && lex_less(msk[ix], msk[iy]);
+}
+
 // grid 1, block kSelThreads: the objective of each of the ncand = kappa * N slots of step s, then
-// sort them and keep the kappa best distinct n-plets as step s + 1.
+// order them and keep the kappa best distinct n-plets as step s + 1.
+//
+// Bitonic sort in LDS of the P >= ncand (a power of two) keys and slot indices.  Thread
+// 1024 j + 64 w + r of a stage with stride <= 64 exchanges entries of the 128-entry chunk
+// 2048 j + 128 w only, so between two such stages wavefront w waits for itself alone; a stage that
+// follows or precedes one with a wider stride (or the fill) waits for the block.  When kappa <= 128
+// only the best 128 entries are needed: once every chunk is sorted (chunk c ascending when c is
+// even, else descending), pairs of chunks are merged keeping the lower half only.  Entry-wise
+// minimum of an ascending and a descending chunk is the 128 smallest of the two as a bitonic
+// sequence; one wavefront sorts it (strides 64..1) ascending or descending as the next merge needs,
+// and the number of chunks halves, until chunk 0 holds the best 128 in order.
 __global__ __launch_bounds__(kSelThreads) void k_greedy_select(GreedyArgs g, int s)
 {
     __shared__ uint64_t key[kSelMax];
@@ -218,11 +238,10 @@ __global__ __launch_bounds__(kSelThreads) void k_greedy_select(GreedyArgs g, int
         idx[i] = i < ncand ? i : -1;
         msk[i] = isnan(o) ? Mask{{0ull, 0ull}} : g.cmask[i];
     }
-    // Thread 1024 j + 64 w + r of a stage with stride <= 64 exchanges elements of the 128-entry
-    // chunk 2048 j + 128 w only, so between two such stages wavefront w waits for itself alone; a
-    // stage that follows or precedes one with a wider stride (or the fill above) waits for the block.
+    const bool topk = g.kappa <= kSelChunk && P > kSelChunk;
+    const int top = topk ? kSelChunk : P;
     bool wide = true;
-    for (int size = 2; size <= P; size <<= 1) {
+    for (int size = 2; size <= top; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             const bool w = stride > 64;
             if (w || wide) __syncthreads();
@@ -233,10 +252,34 @@ __global__ __launch_bounds__(kSelThreads) void k_greedy_select(GreedyArgs g, int
                 const bool asc = (lo & size) == 0;
                 const uint64_t ka = key[lo], kb = key[hi];
                 const int ia = idx[lo], ib = idx[hi];
-                // b before a: smaller key, or equal valid keys and the lexicographically smaller n-plet
-                bool b_first = kb < ka;
-                if (kb == ka && ka != ~0ull) b_first = lex_less(msk[ib], msk[ia]);
-                if (b_first == asc) { key[lo] = kb; key[hi] = ka; idx[lo] = ib; idx[hi] = ia; }
+                if (sel_before(kb, ib, ka, ia, msk) == asc) { key[lo] = kb; key[hi] = ka; idx[lo] = ib; idx[hi] = ia; }
+            }
+        }
+    }
+    if (topk) {
+        // P / 128 <= 32 chunks; merge r pairs chunk 2^r w (ascending) with chunk 2^r w + 2^(r-1)
+        // (descending) in wavefront w, for w below the number of chunks left
+        const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+        const int nch = P / kSelChunk;
+        for (int r = 1; (1 << r) <= nch; ++r) {
+            __syncthreads();
+            if (wv < (nch >> r)) {
+                const int a = (wv << r) * kSelChunk, b = a + (1 << (r - 1)) * kSelChunk;
+                const bool asc = (wv & 1) == 0;
+                for (int j = ln; j < kSelChunk; j += 64) {
+                    const uint64_t ka = key[a + j], kb = key[b + j];
+                    const int ia = idx[a + j], ib = idx[b + j];
+                    if (sel_before(kb, ib, ka, ia, msk)) { key[a + j] = kb; idx[a + j] = ib; }
+                }
+                for (int stride = 64; stride > 0; stride >>= 1) {
+                    wave_sync();
+                    const int lo = a + 2 * ln - (ln & (stride - 1)), hi = lo + stride;
+                    const uint64_t ka = key[lo], kb = key[hi];
+                    const int ia = idx[lo], ib = idx[hi];
+                    if (sel_before(kb, ib, ka, ia, msk) == asc) {
+                        key[lo] = kb; key[hi] = ka; idx[lo] = ib; idx[hi] = ia;
+                    }
+                }
             }
         }
     }
