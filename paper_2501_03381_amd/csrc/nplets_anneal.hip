@@ -16,7 +16,7 @@
 namespace thoi {
 namespace {
 
-constexpr int kAnnealKs = 64;      // row stride of the factorisation scratch (any order up to 64)
+constexpr int kAnnealKs = 65;      // row stride of the factorisation scratch (orders up to 64; odd, so rows start in different LDS banks)
 
 struct Mask {
     uint64_t w[2];

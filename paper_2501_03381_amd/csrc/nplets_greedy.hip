@@ -20,7 +20,7 @@
 namespace thoi {
 namespace {
 
-constexpr int kGreedyKs = 64;
+constexpr int kGreedyKs = 65;          // row stride of the factorisation scratch (odd: rows start in different LDS banks)
 constexpr int kSelThreads = 1024;
 constexpr int kSelMax = 4096;           // candidates of one order that the selection sorts in LDS
 
