@@ -377,12 +377,12 @@ __device__ __forceinline__ FactorOut<double> wave_factor_core(int k, double* __r
 {
     const int lane = threadIdx.x & 63;
     bool ok = true;
-    double lp = 0.0;   // this lane's log pivot (lane j holds log L_jj^2)
+    double pv = 1.0;   // this lane's pivot (lane j holds L_jj^2); its log is taken after the loop
     for (int j = 0; j < k; ++j) {
         const double p = sM[j * ks + j];
         ok = ok && (p > 0.0);
         const double r = rsqrt(p);
-        if (lane == j) { sInv[j] = r; lp = log(p); }
+        if (lane == j) { sInv[j] = r; pv = p; }
         if (lane > j && lane < k) sM[lane * ks + j] *= r;
         __syncthreads();
         if (lane > j && lane < k) {
@@ -391,6 +391,7 @@ __device__ __forceinline__ FactorOut<double> wave_factor_core(int k, double* __r
         }
         __syncthreads();
     }
+    const double lp = lane < k ? log(pv) : 0.0;   // log L_jj^2 in lane j
     double la = 0.0, acc = 0.0;
     if (lane < k) {
         // column `lane` of W = L^-1 by forward substitution; W_mj is kept in the (unused) upper
