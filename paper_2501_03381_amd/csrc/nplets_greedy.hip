@@ -20,7 +20,6 @@
 namespace thoi {
 namespace {
 
-constexpr int kGreedyKs = 65;          // row stride of the factorisation scratch (odd: rows start in different LDS banks)
 constexpr int kSelThreads = 1024;
 constexpr int kSelMax = 4096;           // candidates of one order that the selection sorts in LDS
 
@@ -72,10 +71,12 @@ struct GreedyArgs {
 };
 
 // grid (kappa * N, D), block 64: candidate (p, v) = blockIdx.x / N, % N of step s (order k + 1)
-// in dataset blockIdx.y.
-__global__ __launch_bounds__(64) void k_greedy_eval(GreedyArgs g, int s)
+// in dataset blockIdx.y.  Dynamic LDS: the factorisation block, kc rows of stride kc + 1 for the
+// step's order kc (sized per step, so that short orders leave room for more wavefronts per CU).
+__global__ __launch_bounds__(64) void k_greedy_eval(GreedyArgs g, int s, int kc)
 {
-    __shared__ double sM[64 * kGreedyKs];
+    extern __shared__ double sM[];
+    const int ks = kc + 1;
     __shared__ double sInv[64], sIsd[64], sSeq[128];
     __shared__ int cidx[64];
     const int N = g.N;
@@ -96,6 +97,7 @@ __global__ __launch_bounds__(64) void k_greedy_eval(GreedyArgs g, int s)
         C.w[v >> 6] |= 1ull << (v & 63);
         for (int q = lane; q < p; q += 64) use = use && !subset(sol[q], C);
         use = __all(use);                      // __all over the wavefront: every earlier parent checked
+        use = use && popc(C) <= kc;            // the step's order by construction; the block holds no more
     }
     if (!use) {
         if (lane == 0) meas[slot] = __builtin_nan("");
@@ -124,9 +126,9 @@ __global__ __launch_bounds__(64) void k_greedy_eval(GreedyArgs g, int s)
         sIsd[lane] = dj > 0.0 ? 1.0 / sqrt(dj) : __builtin_nan("");
     }
     __syncthreads();
-    if (lane < k) gather_row(Sig + (int64_t)ci * N, cidx, sIsd, lane, sM + lane * kGreedyKs);
+    if (lane < k) gather_row(Sig + (int64_t)ci * N, cidx, sIsd, lane, sM + lane * ks);
     __syncthreads();
-    const FactorOut<double> f = wave_factor_core(k, sM, kGreedyKs, sInv, sSeq);
+    const FactorOut<double> f = wave_factor_core(k, sM, ks, sInv, sSeq);
     if (lane == 0) {
         const bool ok = f.ok && isfinite(f.ld) && isfinite(f.sa);
         const double TC = -0.5 * f.ld, DTC = 0.5 * (f.ld + f.sa);
@@ -328,8 +330,11 @@ thoi_status launch_greedy(const double* Sigma, int64_t D, int32_t N, int32_t k_f
         if (k_first + t + 1 <= kW2Max)
             hipLaunchKernelGGL(k_greedy_eval_pair, dim3((unsigned)((kappa * N + 1) / 2), (unsigned)D), dim3(64), 0, s, g,
                                (int)t);
-        else
-            hipLaunchKernelGGL(k_greedy_eval, dim3((unsigned)(kappa * N), (unsigned)D), dim3(64), 0, s, g, (int)t);
+        else {
+            const int kc = k_first + t + 1;
+            const size_t lds = (size_t)kc * (size_t)(kc + 1) * sizeof(double);
+            hipLaunchKernelGGL(k_greedy_eval, dim3((unsigned)(kappa * N), (unsigned)D), dim3(64), lds, s, g, (int)t, kc);
+        }
         hipLaunchKernelGGL(k_greedy_select, dim3(1), dim3(kSelThreads), 0, s, g, (int)t);
     }
     return hip_status(hipGetLastError());
