@@ -16,7 +16,6 @@
 namespace thoi {
 namespace {
 
-constexpr int kAnnealKs = 65;      // row stride of the factorisation scratch (orders up to 64; odd, so rows start in different LDS banks)
 
 struct Mask {
     uint64_t w[2];
@@ -169,12 +168,15 @@ __global__ __launch_bounds__(64) void k_anneal_pair(AnnealArgs g, const Mask* __
 }
 
 // grid (kappa), block 64.  INIT: evaluate the starting masks; else iteration t at temperature temp.
-// LDS: sM [64 * kAnnealKs] | sInv [64] | sIsd [64] | cidx [64] | prop.
+// Dynamic LDS: the factorisation block, kmax rows of stride kmax + 1 (sized for the largest order a
+// chain reaches, so that smaller maxima leave room for more wavefronts per CU); static: sInv [64] |
+// sIsd [64] | cidx [64] | prop.
 template <bool INIT>
 __global__ __launch_bounds__(64) void k_anneal(AnnealArgs g, const Mask* __restrict__ masks0, int64_t t,
                                                double temp)
 {
-    __shared__ double sM[64 * kAnnealKs];
+    extern __shared__ double sM[];
+    const int ks = g.kmax + 1;
     __shared__ double sInv[64], sIsd[64];
     __shared__ int cidx[64];
     __shared__ Mask sprop;
@@ -185,8 +187,10 @@ __global__ __launch_bounds__(64) void k_anneal(AnnealArgs g, const Mask* __restr
     if (lane == 0) sprop = chain_neighbour(g, INIT, masks0, c, t);
     __syncthreads();
     const Mask p = sprop;
+    // every state holds k_min..k_max members; the clamp keeps a starting mask outside that range
+    // in bounds of the block
     int k = popc(p);
-    k = k < 64 ? k : 64;
+    k = k < g.kmax ? k : g.kmax;
     // the block's variables and 1/sqrt of their variances, then the correlation block row by row:
     // R_ij = (Sigma_ij / sqrt(Sigma_ii)) / sqrt(Sigma_jj), unit diagonal
     int ci = 0;
@@ -197,9 +201,9 @@ __global__ __launch_bounds__(64) void k_anneal(AnnealArgs g, const Mask* __restr
         sIsd[lane] = dj > 0.0 ? 1.0 / sqrt(dj) : __builtin_nan("");
     }
     __syncthreads();
-    if (lane < k) gather_row(g.Sigma + (int64_t)ci * N, cidx, sIsd, lane, sM + lane * kAnnealKs);
+    if (lane < k) gather_row(g.Sigma + (int64_t)ci * N, cidx, sIsd, lane, sM + lane * ks);
     __syncthreads();
-    const FactorOut<double> f = wave_factor_core(k, sM, kAnnealKs, sInv);
+    const FactorOut<double> f = wave_factor_core(k, sM, ks, sInv);
     if (lane == 0) chain_update(g, INIT, c, t, temp, p, f);
 }
 
@@ -232,13 +236,14 @@ thoi_status launch_anneal(const double* Sigma, int32_t N, const uint64_t* masks0
     // every order a chain can reach is at most k_max: the pair factorisation when it fits
     const bool pair = k_max <= kW2Max;
     const dim3 grid(pair ? (unsigned)((kappa + 1) / 2) : (unsigned)kappa);
+    const size_t lds = pair ? 0 : (size_t)k_max * (size_t)(k_max + 1) * sizeof(double);
     if (pair) hipLaunchKernelGGL(k_anneal_pair<true>, grid, dim3(64), 0, s, g, m0, (int64_t)0, 0.0);
-    else hipLaunchKernelGGL(k_anneal<true>, grid, dim3(64), 0, s, g, m0, (int64_t)0, 0.0);
+    else hipLaunchKernelGGL(k_anneal<true>, grid, dim3(64), lds, s, g, m0, (int64_t)0, 0.0);
     // the temperature of iteration t is T0 multiplied by alpha t times, one product at a time
     double temp = T0;
     for (int32_t t = 0; t < iters; ++t) {
         if (pair) hipLaunchKernelGGL(k_anneal_pair<false>, grid, dim3(64), 0, s, g, m0, (int64_t)t, temp);
-        else hipLaunchKernelGGL(k_anneal<false>, grid, dim3(64), 0, s, g, m0, (int64_t)t, temp);
+        else hipLaunchKernelGGL(k_anneal<false>, grid, dim3(64), lds, s, g, m0, (int64_t)t, temp);
         temp *= alpha;
     }
     return hip_status(hipGetLastError());
