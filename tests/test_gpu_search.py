@@ -84,6 +84,22 @@ def test_greedy_device_matches_host_loop(env):
                 assert np.abs(got[k][1] - ref[k][1]).max() < 1e-9, k
 
 
+def test_greedy_device_selection_paths(env):
+    """Each path of the device selection against the host-driven loop on latent_20: the whole
+    bitonic sort (kappa N <= 128, and kappa > 128), and the chunk sort with pairwise best-half
+    merges (kappa <= 128; 2560 slots, sorted as 4096 entries in 32 chunks)."""
+    torch, search, osearch, synth, orc = env
+    S = orc.gc_covariance(synth.latent_20())
+    for k0, k1, kappa in ((2, 6, 4), (2, 5, 160), (2, 6, 128)):
+        for maximize in (True, False):
+            say(f"greedy selection N=20 orders {k0}..{k1} kappa {kappa} maximize={maximize}: device vs host loop")
+            got = search.greedy(dev(torch, S), k0, k1, kappa=kappa, maximize=maximize, on_device=True)
+            ref = search.greedy(dev(torch, S), k0, k1, kappa=kappa, maximize=maximize, on_device=False)
+            for k in range(k0, k1 + 1):
+                assert np.array_equal(got[k][0], ref[k][0]), (kappa, k)
+                assert np.abs(got[k][1] - ref[k][1]).max() < 1e-9, (kappa, k)
+
+
 def _gpu_gradients(torch, S, sols):
     from paper_2501_03381_amd import api
     kappa, N = len(sols), S.shape[0]
